@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the sample-based MSSC hot path on one MI355X.
+
+Workload (k = 25, d = 32): m = 10^7 FP32 points from a 25-component
+Gaussian mixture (centres in [-20, 20]^32, diagonal std U[0.5, 3]), W =
+1,024 workers each clustering a sample of s = 10,000 points per step.
+
+One step = one round of the competitive strategy (Algorithm 3) for all
+workers, i.e. the whole hot path once: sample draw for every worker,
+K-means++ re-seeding of degenerate centroids (a full seeding on the first
+round), Lloyd passes to the stop rule, keep-the-best per worker, selection
+of the best worker, and the full-data assignment with its FP64 objective.
+
+metric: sample-point-iters/s = sum over samples of s x assignment passes,
+divided by the wall time of the timed steps (inputs resident in HBM).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=10_000_000)
+    ap.add_argument("--workers", type=int, default=1024)
+    ap.add_argument("--s", type=int, default=10_000)
+    ap.add_argument("--k", type=int, default=25)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the oracle CPU baseline (0 disables it)")
+    ap.add_argument("--seed", type=int, default=1)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
+                                   "supported (samples would shard across GPUs, see DESIGN.md)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2311_04517_amd import api
+
+    dev = "cuda"
+    torch.cuda.init()
+    print(f"[bench] {api.version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr,
+          flush=True)
+    t_gen = time.perf_counter()
+    mx = synthetic.metric_set(m=args.m, device=dev)
+    X = mx.X
+    torch.cuda.synchronize()
+    print(f"[bench] data {tuple(X.shape)} generated in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    m, d = X.shape
+    W, s, k = args.workers, args.s, args.k
+
+    C_inc = torch.full((W, k, d), float("nan"), dtype=torch.float32, device=dev)
+    f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device=dev)
+    C = torch.empty_like(C_inc)
+    idx = torch.empty(W * s, dtype=torch.int64, device=dev)
+    labels = torch.empty(m, dtype=torch.int32, device=dev)
+    counts = torch.empty(k, dtype=torch.int64, device=dev)
+    sse = torch.empty(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    ev = {name: [] for name in ("lloyd", "assign")}
+
+    def step(r, timed):
+        ids = [r * W + w for w in range(W)]
+        desc, idx_len, _ = api.make_desc([s] * W, [k] * W, seed=args.seed, sample_id=ids, d=d)
+        api.draw_samples(m, desc, idx_len, out=idx)
+        C.copy_(C_inc)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        f, it, _ = api.lloyd_batch(X, idx, desc, C)
+        e1.record(stream)
+        api.keep_best(C, f, C_inc, f_inc, k, d)
+        Cb, fb, wb = api.select_best(C_inc, f_inc, k, d)
+        e2.record(stream)
+        api.assign_sse(X, Cb, labels=labels, counts=counts, sse=sse)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e3.record(stream)
+        if timed:
+            ev["lloyd"].append((e0, e1))
+            ev["assign"].append((e2, e3))
+        return it, idx.clone() if r == 0 else None
+
+    r = 0
+    for _ in range(args.warmup):
+        step(r, False)
+        r += 1
+    torch.cuda.synchronize()
+    print(f"[bench] {args.warmup} warmup step(s) done", file=sys.stderr, flush=True)
+    its = []
+    f_before = f_inc.clone()
+    C_before = C_inc.clone()
+    r_first_timed = r
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        it, _ = step(r, True)
+        its.append(it)
+        r += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    passes = np.array([int(t.sum().item()) for t in its])
+    spi = int(passes.sum()) * s
+    value = spi / elapsed
+    t_lloyd = np.mean([a.elapsed_time(b) for a, b in ev["lloyd"]]) / 1e3
+    t_assign = np.mean([a.elapsed_time(b) for a, b in ev["assign"]]) / 1e3
+    spi_per_step = passes.mean() * s
+    lloyd_gbs = spi_per_step * 4 * d / t_lloyd / 1e9
+    assign_gbs = (m * 4 * d + m * 4) / t_assign / 1e9
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s; passes/step {passes.tolist()}; "
+          f"lloyd {t_lloyd * 1e3:.2f} ms ({lloyd_gbs:.0f} GB/s algorithmic), "
+          f"assign {t_assign * 1e3:.3f} ms ({assign_gbs:.0f} GB/s), SSE {sse.item():.6e}",
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(X, C_before, r_first_timed, args, m, d, W, s, k)
+
+    out = {
+        "metric": "sample-point-iters/sec (k=25,d=32)",
+        "value": value,
+        "unit": "sample-point-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round",
+                   "m": m, "d": d, "k": k, "s": s, "workers": W, "strategy": "competitive",
+                   "passes_per_step": float(passes.mean())},
+        "roofline": {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_lloyd_resident<32,256>",
+                     "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
+                     "avg_launch_ms": t_lloyd * 1e3},
+        "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,
+                       "frac": assign_gbs / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
+    """The FP64 oracle on a bounded sample of the same workload: the first
+    samples of the first timed round, from the same incumbents, on the
+    host's cores (samples run side by side)."""
+    import numpy as np
+
+    import oracle
+    from paper_2311_04517_amd import api
+
+    n_threads = max(1, min(16, os.cpu_count() or 1))
+    Xn = X.cpu().numpy()
+    done_spi, done_t, done_n = 0, 0.0, 0
+    per = n_threads
+    while done_t < args.cpu_seconds and done_n + per <= W:
+        ids = [r * W + w for w in range(done_n, done_n + per)]
+        idx = np.concatenate([oracle.draw_sample(m, s, args.seed, i) for i in ids])
+        Cb = C_start[done_n:done_n + per].double().cpu().numpy().ravel().copy()
+        desc = dict(idx_offset=np.arange(per) * s, s=[s] * per, k=[k] * per,
+                    c_offset=np.arange(per) * k * d, seed=[args.seed] * per, sample_id=ids)
+        t0 = time.perf_counter()
+        o = oracle.lloyd_batch(Xn, idx, desc, Cb, n_threads=n_threads)
+        done_t += time.perf_counter() - t0
+        done_spi += int(o["iters"].sum()) * s
+        done_n += per
+    del api
+    return {"value": done_spi / done_t, "unit": "sample-point-iters/s", "cores": n_threads,
+            "kind": "oracle",
+            "sample": f"{done_n} of the {W} samples of one round (same inputs and incumbents), "
+                      f"{done_t:.1f}s of CPU work on {n_threads} threads"}
+
+
+if __name__ == "__main__":
+    main()

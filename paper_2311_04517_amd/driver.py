@@ -1,0 +1,117 @@
+"""Worker loops of the method built from the C-ABI calls.
+
+``worker_loop`` is one worker of Algorithm 3 (the sequential form of
+Section 3).  ``strategy_rounds`` runs W workers per round as one batched
+launch: competitive (Algorithm 3: each worker restarts from its own
+incumbent), cooperative (Algorithm 4: every worker restarts from the best
+incumbent) and hybrid (Algorithm 5: competitive rounds, then cooperative
+rounds).  All arithmetic runs in the library's kernels; torch only holds
+memory and copies incumbents between buffers.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import api
+
+
+@dataclass
+class WorkerResult:
+    C: torch.Tensor          # k x d incumbent
+    f_hat: torch.Tensor      # [1] float64
+    f_samples: torch.Tensor  # n_samples float64
+    iters: torch.Tensor      # n_samples int32
+    labels: torch.Tensor | None
+    counts: torch.Tensor | None
+    sse: torch.Tensor | None
+
+
+def worker_loop(X: torch.Tensor, *, s: int, k: int, n_samples: int, seed: int, max_iter=300,
+                rel_tol=1e-4, precision=api.PREC_FP32, final_assign=True) -> WorkerResult:
+    """C_w <- all degenerate; for t < n_samples: sample t, K-means from C_w
+    (degenerate rows re-seeded first), keep the best; then assign X."""
+    m, d = X.shape
+    dev = X.device
+    C_w = torch.full((k, d), float("nan"), dtype=torch.float32, device=dev)
+    f_hat = torch.full((1,), float("inf"), dtype=torch.float64, device=dev)
+    C = torch.empty((k, d), dtype=torch.float32, device=dev)
+    idx = torch.empty(s, dtype=torch.int64, device=dev)
+    f_s = torch.empty(n_samples, dtype=torch.float64, device=dev)
+    it_s = torch.empty(n_samples, dtype=torch.int32, device=dev)
+    for t in range(n_samples):
+        api.draw_sample(m, s, seed, t, out=idx)
+        C.copy_(C_w)
+        desc, _, _ = api.make_desc([s], [k], seed=seed, sample_id=[t], d=d)
+        api.lloyd_batch(X, idx, desc, C, max_iter=max_iter, rel_tol=rel_tol, precision=precision,
+                        f_out=f_s[t:t + 1], iters_out=it_s[t:t + 1])
+        api.keep_best(C, f_s[t:t + 1], C_w, f_hat, k, d)
+    labels = counts = sse = None
+    if final_assign:
+        labels, counts, sse = api.assign_sse(X, C_w, precision=precision)
+    return WorkerResult(C_w, f_hat, f_s, it_s, labels, counts, sse)
+
+
+@dataclass
+class StrategyState:
+    C_inc: torch.Tensor   # W x k x d incumbents
+    f_inc: torch.Tensor   # W float64
+    round: int = 0
+
+
+def new_state(W: int, k: int, d: int, device) -> StrategyState:
+    return StrategyState(
+        torch.full((W, k, d), float("nan"), dtype=torch.float32, device=device),
+        torch.full((W,), float("inf"), dtype=torch.float64, device=device))
+
+
+def strategy_round(X, state: StrategyState, *, s: int, k: int, seed: int, cooperative: bool,
+                   max_iter=300, rel_tol=1e-4, precision=api.PREC_FP32, work=None):
+    """One round of W workers as one batched launch.  Worker w processes
+    sample id round*W + w.  Competitive: starts from its own incumbent;
+    cooperative: from the best incumbent (lowest index on ties).  Returns
+    (f, iters) of the round."""
+    m, d = X.shape
+    W = state.f_inc.numel()
+    dev = X.device
+    if work is None:
+        work = {}
+    C = work.get("C")
+    if C is None or C.shape != state.C_inc.shape:
+        C = work["C"] = torch.empty_like(state.C_inc)
+    if cooperative:
+        Cb, _, _ = api.select_best(state.C_inc, state.f_inc, k, d)
+        C.copy_(Cb.unsqueeze(0).expand(W, k, d))
+    else:
+        C.copy_(state.C_inc)
+    ids = [state.round * W + w for w in range(W)]
+    desc, idx_len, _ = api.make_desc([s] * W, [k] * W, seed=seed, sample_id=ids, d=d)
+    idx = work.get("idx")
+    if idx is None or idx.numel() != idx_len:
+        idx = work["idx"] = torch.empty(idx_len, dtype=torch.int64, device=dev)
+    api.draw_samples(m, desc, idx_len, out=idx)
+    f, it, _ = api.lloyd_batch(X, idx, desc, C, max_iter=max_iter, rel_tol=rel_tol,
+                               precision=precision)
+    api.keep_best(C, f, state.C_inc, state.f_inc, k, d)
+    state.round += 1
+    return f, it
+
+
+def run_strategy(X, *, W: int, s: int, k: int, seed: int, n_rounds: int, strategy: str,
+                 n_competitive: int = 0, max_iter=300, rel_tol=1e-4, precision=api.PREC_FP32):
+    """HPClust-competitive / -cooperative / -hybrid over n_rounds rounds;
+    hybrid runs n_competitive competitive rounds first.  Returns the state,
+    the best incumbent and the final assignment."""
+    m, d = X.shape
+    state = new_state(W, k, d, X.device)
+    work = {}
+    for r in range(n_rounds):
+        coop = strategy == "cooperative" or (strategy == "hybrid" and r >= n_competitive)
+        if strategy not in ("competitive", "cooperative", "hybrid"):
+            raise ValueError(strategy)
+        strategy_round(X, state, s=s, k=k, seed=seed, cooperative=coop, max_iter=max_iter,
+                       rel_tol=rel_tol, precision=precision, work=work)
+    Cb, fb, wb = api.select_best(state.C_inc, state.f_inc, k, d)
+    labels, counts, sse = api.assign_sse(X, Cb, precision=precision)
+    return state, Cb, fb, wb, labels, counts, sse

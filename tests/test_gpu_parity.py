@@ -1,0 +1,344 @@
+"""Parity of the gfx950 path with the FP64 oracle, through the C ABI.
+
+Sizes finish in seconds on the oracle yet span many workgroups, chunks and
+a ragged tail.  Decisions that sit within rounding of a threshold (near
+ties, D^2 draws near a prefix boundary, near-equal candidate potentials,
+stop tests near rel_tol) are reported by the oracle; comparisons that
+depend on them either exempt the affected points or use another seed, as
+described in tests/tolerances.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from tests.tolerances import (F_REL, SSE_REL, TIE_REL, assert_centroids, assert_labels,
+                              diag_clean, rel)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hp():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_2311_04517_amd import api
+
+    api.version()  # raises if the HIP library is not built
+    return api
+
+
+def _mix(m, d, n_comp, seed, box=10.0, std=1.0):
+    mx = synthetic.gaussian_mixture(m, d, n_comp, seed=seed, centre_box=box, std=std)
+    return mx.X.numpy(), mx.X.cuda()
+
+
+def _desc_np(desc):
+    n = len(desc)
+    return dict(idx_offset=[desc[b].idx_offset for b in range(n)], s=[desc[b].s for b in range(n)],
+                k=[desc[b].k for b in range(n)], c_offset=[desc[b].c_offset for b in range(n)],
+                seed=[desc[b].seed for b in range(n)], sample_id=[desc[b].sample_id for b in range(n)])
+
+
+# ---------------------------------------------------------------- sampler
+@pytest.mark.parametrize("m,s,seed,sid", [(1, 1, 0, 0), (1000, 7, 3, 1), (10**9 + 7, 4097, 12, 5),
+                                          (2**40 + 3, 1000, 2**63 + 5, 2**40)])
+def test_draw_sample_bit_exact(hp, orc, m, s, seed, sid):
+    g = hp.draw_sample(m, s, seed, sid).cpu().numpy()
+    assert np.array_equal(g, orc.draw_sample(m, s, seed, sid))
+
+
+def test_draw_samples_batch_bit_exact(hp, orc):
+    ss = [5, 1, 300, 4096, 17]
+    desc, idx_len, _ = hp.make_desc(ss, [1] * 5, seed=9, sample_id=[0, 1, 7, 3, 2**33], d=4)
+    g = hp.draw_samples(123457, desc, idx_len).cpu().numpy()
+    ref = np.concatenate([orc.draw_sample(123457, s, 9, sid)
+                          for s, sid in zip(ss, [0, 1, 7, 3, 2**33])])
+    assert np.array_equal(g, ref)
+
+
+# ---------------------------------------------------------------- assign + SSE
+@pytest.mark.parametrize("d", [3, 8, 16, 32, 64, 100])
+def test_assign_sse_parity(hp, orc, d):
+    m, k = 70_001, 13
+    Xn, Xg = _mix(m, d, 9, seed=d)
+    rng = np.random.default_rng(d)
+    Cn = (Xn[rng.integers(0, m, size=k)] + rng.normal(0, 0.5, size=(k, d))).astype(np.float32)
+    Cn[4] = np.nan  # a degenerate row is skipped
+    lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda())
+    o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
+    assert_labels(lab.cpu().numpy(), o["labels"], o["margins"])
+    lg = lab.cpu().numpy()
+    assert (lg != 4).all()
+    assert np.array_equal(cnt.cpu().numpy(), np.bincount(lg, minlength=k))
+    assert rel(sse.item(), o["sse"]) <= SSE_REL
+
+
+def test_assign_sse_small_and_ragged(hp, orc):
+    for m, k in [(1, 1), (5, 3), (257, 2), (1023, 40)]:
+        Xn, Xg = _mix(m, 5, 3, seed=m)
+        Cn = Xn[np.arange(k) % m].copy()
+        if k > 1:
+            Cn[-1] += 0.25
+        lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda())
+        o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
+        assert_labels(lab.cpu().numpy(), o["labels"], o["margins"])
+        assert rel(sse.item(), o["sse"]) <= SSE_REL or (o["sse"] == 0 and sse.item() == 0)
+
+
+def test_assign_sse_deterministic(hp):
+    Xn, Xg = _mix(200_000, 32, 10, seed=1)
+    C = Xg[:25].clone()
+    a = hp.assign_sse(Xg, C)
+    b = hp.assign_sse(Xg, C)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2].item() == b[2].item()
+
+
+# ---------------------------------------------------------------- seeding
+def _seed_case(hp, orc, Xn, Xg, s, k, seed, sid, call, Cin=None, n_cand=3):
+    m, d = Xn.shape
+    idx = orc.draw_sample(m, s, seed, sid)
+    Co, cho, g = orc.kmeanspp(Xn, idx, k, seed=seed, sample_id=sid, call_id=call, n_cand=n_cand,
+                              C=Cin)
+    Cg_in = (torch.full((k, d), float("nan")) if Cin is None
+             else torch.from_numpy(np.asarray(Cin, dtype=np.float32))).cuda()
+    Cg, chg = hp.seed_kmeanspp(Xg, torch.from_numpy(idx).cuda(), k, seed=seed, sample_id=sid,
+                               call_id=call, n_cand=n_cand, C=Cg_in)
+    return Co, cho, g, Cg.cpu().numpy(), chg.cpu().numpy()
+
+
+@pytest.mark.parametrize("d,s,k", [(8, 2000, 10), (32, 10_000, 25), (5, 777, 7), (64, 3000, 40)])
+def test_seed_kmeanspp_bit_exact(hp, orc, d, s, k):
+    Xn, Xg = _mix(40_000, d, 12, seed=100 + d)
+    clean = 0
+    for call in range(6):
+        Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, s, k, 5, 1, call)
+        if g["min_draw_margin"] < 1e-5 or g["min_cand_margin"] < 1e-5:
+            continue
+        clean += 1
+        assert np.array_equal(chg, cho), (call, chg, cho)
+        assert np.array_equal(Cg.astype(np.float64), Co)
+    assert clean >= 3
+
+
+def test_seed_kmeanspp_partial_and_candidates(hp, orc):
+    Xn, Xg = _mix(20_000, 16, 8, seed=7)
+    rng = np.random.default_rng(0)
+    for n_cand in (1, 2, 3, 4):
+        Cin = Xn[rng.integers(0, 20_000, size=9)].astype(np.float64)
+        Cin[[1, 4, 8]] = np.nan
+        Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 1500, 9, 11, 2, n_cand, Cin, n_cand)
+        if g["min_draw_margin"] < 1e-5 or g["min_cand_margin"] < 1e-5:
+            continue
+        assert np.array_equal(chg, cho)
+        assert (chg[[0, 2, 3, 5, 6, 7]] == -1).all()
+        assert np.array_equal(Cg.astype(np.float64), Co)
+
+
+def test_seed_zero_weight_and_duplicates(hp, orc):
+    # every sample point coincides with the one valid centre: W = 0 path
+    X = np.zeros((50, 4), dtype=np.float32)
+    Cin = np.full((3, 4), np.nan)
+    Cin[0] = 0.0
+    Co, cho, g, Cg, chg = _seed_case(hp, orc, X, torch.from_numpy(X).cuda(), 20, 3, 4, 0, 0, Cin)
+    assert g["n_zero_weight"] == 2
+    assert np.array_equal(chg, cho)
+    # k = s distinct points: every point chosen once
+    Xn, Xg = _mix(1000, 3, 2, seed=3)
+    Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 64, 64, 2, 0, 0)
+    if g["min_draw_margin"] >= 1e-5 and g["min_cand_margin"] >= 1e-5:
+        assert np.array_equal(chg, cho)
+
+
+# ---------------------------------------------------------------- Lloyd
+def _lloyd_gpu(hp, Xg, idx, desc, Cin, **kw):
+    Cg = torch.from_numpy(np.asarray(Cin, dtype=np.float32).ravel().copy()).cuda()
+    f, it, lab = hp.lloyd_batch(Xg, torch.from_numpy(idx).cuda(), desc, Cg, want_labels=True, **kw)
+    return Cg.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()
+
+
+@pytest.mark.parametrize("d,s,k", [(8, 2000, 10), (32, 10_000, 25), (16, 5003, 5)])
+def test_lloyd_teacher_forced_two_passes(hp, orc, d, s, k):
+    """From the same valid centroids: one update and the next assignment."""
+    Xn, Xg = _mix(60_000, d, 15, seed=200 + d, box=10.0, std=1.5)
+    idx = orc.draw_sample(60_000, s, 3, 0)
+    rng = np.random.default_rng(d)
+    C0 = Xn[idx[rng.choice(s, size=k, replace=False)]].astype(np.float64)
+    ro = orc.lloyd(Xn, idx, k, C0, seed=3, sample_id=0, max_iter=2, rel_tol=0.0,
+                   want_margins=True)
+    desc, _, _ = hp.make_desc([s], [k], seed=3, sample_id=[0], d=d)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0, max_iter=2, rel_tol=0.0)
+    assert itg[0] == ro.iters == 2
+    if ro.diag["n_label_ties"] == 0:
+        assert_centroids(Cg.reshape(k, d), ro.C, Xn[idx])
+        assert rel(fg[0], ro.f) <= F_REL
+    assert_labels(lg, ro.labels, ro.margins)
+
+
+@pytest.mark.parametrize("d,s,k,mseed", [(8, 2000, 10, 0), (32, 10_000, 25, 1), (12, 3001, 6, 2)])
+def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed):
+    """Cold start (all rows degenerate): K-means++ then passes to the stop
+    rule; exact pass counts and labels on seeds whose oracle run is clean."""
+    Xn, Xg = _mix(50_000, d, 10, seed=300 + mseed)
+    clean = 0
+    for sid in range(6):
+        idx = orc.draw_sample(50_000, s, 17, sid)
+        ro = orc.lloyd(Xn, idx, k, seed=17, sample_id=sid, want_margins=True)
+        desc, _, _ = hp.make_desc([s], [k], seed=17, sample_id=[sid], d=d)
+        Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, np.full((k, d), np.nan))
+        assert np.isfinite(Cg).all() and 1 <= itg[0] <= 300
+        if not diag_clean(ro.diag):
+            continue
+        clean += 1
+        assert itg[0] == ro.iters, (sid, itg[0], ro.iters)
+        assert rel(fg[0], ro.f) <= F_REL
+        assert_centroids(Cg.reshape(k, d), ro.C, Xn[idx])
+        assert_labels(lg, ro.labels, ro.margins)
+    assert clean >= 2, "too few clean seeds"
+
+
+def test_lloyd_reseeds_emptied_cluster(hp, orc):
+    """A centroid far from every point empties in pass 1 and is re-seeded
+    (stream RESEED, call 1) at the top of pass 2."""
+    Xn, Xg = _mix(30_000, 6, 4, seed=9, box=30.0)
+    s, k = 3000, 5
+    idx = orc.draw_sample(30_000, s, 8, 4)
+    C0 = Xn[idx[:k]].astype(np.float64)
+    C0[2] = 1e4
+    ro = orc.lloyd(Xn, idx, k, C0, seed=8, sample_id=4, want_margins=True)
+    assert ro.diag["n_seed_calls"] >= 1
+    desc, _, _ = hp.make_desc([s], [k], seed=8, sample_id=[4], d=6)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0)
+    if diag_clean(ro.diag):
+        assert itg[0] == ro.iters and rel(fg[0], ro.f) <= F_REL
+        assert_centroids(Cg.reshape(k, 6), ro.C, Xn[idx])
+        assert_labels(lg, ro.labels, ro.margins)
+
+
+def test_lloyd_degenerate_cases(hp, orc):
+    # all points identical -> f == 0 after the first pass
+    X = np.ones((100, 4), dtype=np.float32)
+    idx = np.arange(100, dtype=np.int64)
+    desc, _, _ = hp.make_desc([100], [3], seed=1, sample_id=[0], d=4)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, torch.from_numpy(X).cuda(), idx, desc, np.full((3, 4), np.nan))
+    ro = orc.lloyd(X, idx, 3, seed=1)
+    assert fg[0] == 0.0 and itg[0] == 1 == ro.iters and np.array_equal(lg, ro.labels)
+    # k = 1 closed form and max_iter = 1
+    Xn, Xg = _mix(5000, 7, 3, seed=2)
+    idx = orc.draw_sample(5000, 999, 2, 0)
+    desc, _, _ = hp.make_desc([999], [1], seed=2, sample_id=[0], d=7)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, np.full((1, 7), np.nan))
+    S = Xn[idx].astype(np.float64)
+    assert itg[0] == 3
+    assert rel(fg[0], ((S - S.mean(0)) ** 2).sum()) <= F_REL
+    assert_centroids(Cg.reshape(1, 7), S.mean(0, keepdims=True), S)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, np.full((1, 7), np.nan), max_iter=1)
+    ro = orc.lloyd(Xn, idx, 1, seed=2, max_iter=1)
+    assert itg[0] == 1 and rel(fg[0], ro.f) <= F_REL and np.array_equal(Cg.reshape(1, 7), ro.C)
+
+
+def test_lloyd_batch_uneven(hp, orc):
+    """Many samples of uneven (s, k), cold and warm starts, in one launch."""
+    Xn, Xg = _mix(80_000, 10, 12, seed=11, box=12.0)
+    rng = np.random.default_rng(5)
+    n = 24
+    ss = rng.integers(50, 6000, size=n)
+    ks = np.minimum(rng.integers(1, 30, size=n), ss)
+    desc, idx_len, c_len = hp.make_desc(ss, ks, seed=21, sample_id=np.arange(n) + 100, d=10)
+    dn = _desc_np(desc)
+    idx = np.concatenate([orc.draw_sample(80_000, int(s), 21, 100 + b) for b, s in enumerate(ss)])
+    C0 = np.full(c_len, np.nan)
+    for b in range(0, n, 2):  # even samples warm-start from sample points, one row degenerate
+        co, k = dn["c_offset"][b], dn["k"][b]
+        blk = Xn[idx[dn["idx_offset"][b]:dn["idx_offset"][b] + k]].astype(np.float64)
+        blk[0] = np.nan
+        C0[co:co + k * 10] = blk.ravel()
+    Co = C0.copy()
+    ro = orc.lloyd_batch(Xn, idx, dn, Co, want_labels=True, n_threads=4)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0)
+    clean = 0
+    for b in range(n):
+        io, s, k, co = dn["idx_offset"][b], dn["s"][b], dn["k"][b], dn["c_offset"][b]
+        S = Xn[idx[io:io + s]]
+        cg = Cg[co:co + k * 10].reshape(k, 10)
+        assert np.isfinite(cg).all() and 1 <= itg[b] <= 300
+        # the returned objective is the objective of the returned centroids
+        chk = orc.assign_sse(S, cg.astype(np.float64), want_margins=True)
+        assert rel(fg[b], chk["sse"]) <= F_REL
+        assert_labels(lg[io:io + s], chk["labels"], chk["margins"])
+        if not diag_clean(ro["diag"][b]):
+            continue
+        clean += 1
+        assert itg[b] == ro["iters"][b]
+        assert rel(fg[b], ro["f"][b]) <= F_REL
+        assert_centroids(cg, Co[co:co + k * 10].reshape(k, 10), S)
+    assert clean >= n // 2
+
+
+def test_lloyd_batch_deterministic(hp, orc):
+    Xn, Xg = _mix(50_000, 32, 25, seed=4, box=20.0, std=2.0)
+    n, s, k = 40, 4000, 25
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=5, sample_id=np.arange(n), d=32)
+    idx = hp.draw_samples(50_000, desc, idx_len)
+    outs = []
+    for _ in range(2):
+        C = torch.full((c_len,), float("nan"), device="cuda")
+        f, it, lab = hp.lloyd_batch(Xg, idx, desc, C, want_labels=True)
+        outs.append((C.clone(), f.clone(), it.clone(), lab.clone()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------- keep-best / select-best
+def test_keep_and_select_best(hp):
+    W, k, d = 37, 5, 3
+    rng = np.random.default_rng(1)
+    Cn = torch.from_numpy(rng.normal(size=(W, k, d)).astype(np.float32)).cuda()
+    Ci = torch.from_numpy(rng.normal(size=(W, k, d)).astype(np.float32)).cuda()
+    fn = torch.from_numpy(rng.uniform(size=W)).cuda()
+    fi = torch.from_numpy(rng.uniform(size=W)).cuda()
+    fi[3] = fn[3]  # tie: strict comparison keeps the incumbent
+    fi[0] = float("inf")
+    Ci0, fi0 = Ci.clone(), fi.clone()
+    upd = hp.keep_best(Cn, fn, Ci, fi, k, d, want_updated=True)
+    take = (fn < fi0).cpu().numpy()
+    assert np.array_equal(upd.cpu().numpy(), take.astype(np.int32))
+    assert not take[3] and take[0]
+    exp = torch.where(torch.from_numpy(take).cuda()[:, None, None], Cn, Ci0)
+    assert torch.equal(Ci, exp)
+    assert torch.equal(fi, torch.minimum(fi0, fn))
+    fi[7] = -1.0
+    fi[20] = -1.0
+    Cb, fb, wb = hp.select_best(Ci, fi, k, d)
+    assert wb.item() == 7 and fb.item() == -1.0 and torch.equal(Cb, Ci[7])
+
+
+# ---------------------------------------------------------------- worker loop
+def test_worker_loop_plain_small_config(hp, orc):
+    """The plain small workload (m = 50,000, d = 8, k = 10, s = 2,000, 8
+    samples, K-means++, max 300 passes, tol 1e-4, then full assignment)."""
+    from paper_2311_04517_amd import driver
+
+    mx = synthetic.plain_small()
+    Xn = mx.X.numpy()
+    Xg = mx.X.cuda()
+    clean = 0
+    for seed in range(4):
+        wo = orc.worker_loop(Xn, s=2000, k=10, n_samples=8, seed=seed)
+        wg = driver.worker_loop(Xg, s=2000, k=10, n_samples=8, seed=seed)
+        torch.cuda.synchronize()
+        fo = wo["f_samples"]
+        keep_margin = min(abs(fo[t] - fo[:t].min()) / fo[:t].min() for t in range(1, 8))
+        if not diag_clean(wo["diag"]) or keep_margin < 1e-5:
+            continue
+        clean += 1
+        assert np.array_equal(wg.iters.cpu().numpy(), wo["iters"])
+        for t in range(8):
+            assert rel(wg.f_samples[t].item(), fo[t]) <= F_REL
+        assert_centroids(wg.C.cpu().numpy(), wo["C"], Xn)
+        assert rel(wg.sse.item(), wo["sse"]) <= SSE_REL
+        full = orc.assign_sse(Xn, wo["C"], want_margins=True)
+        assert_labels(wg.labels.cpu().numpy(), wo["labels"], full["margins"])
+        assert np.array_equal(wg.counts.cpu().numpy(), np.bincount(wg.labels.cpu().numpy(),
+                                                                   minlength=10))
+    assert clean >= 1
