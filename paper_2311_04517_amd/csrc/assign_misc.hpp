@@ -41,11 +41,20 @@ __global__ void k_draw_batch(int64_t m, const hpc_sample_desc* __restrict__ desc
 // ---------------------------------------------------------------------------
 // Full assignment + objective (Section 3 final step; Eq. (1)).  HBM-bound
 // stream over the rows of X: each thread takes whole rows (grid-stride),
-// centroids are staged in LDS (zero padded to D, degenerate rows flagged),
-// per-cluster counts go to an LDS histogram, and the objective is an FP64
-// per-thread partial reduced per workgroup in fixed order, then across
-// workgroups by k_reduce_partials in fixed order.
+// centroids are staged in LDS (FP32 for the screening, FP64 for the exact
+// distance; zero padded to D, degenerate rows flagged).  The FP32 screening
+// winner is certified (the centroids are exact in FP32 here, so only the
+// arithmetic bound applies) or re-decided in FP64; the objective adds the
+// FP64 distance to the chosen centroid.  Counts go to an LDS histogram; the
+// objective is an FP64 per-thread partial reduced per workgroup in fixed
+// order, then across workgroups by k_reduce_partials in fixed order.
 // ---------------------------------------------------------------------------
+template <int D>
+__host__ __device__ inline size_t assign_lds_bytes(int k, int nt) {
+    return (size_t)k * D * 8 + (((size_t)k * D * 4 + (size_t)k * 8 + 15) / 16) * 16 +
+           (size_t)(nt / kWave) * 8;
+}
+
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, int64_t m, int d,
                                                    const float* __restrict__ C, int k,
@@ -53,20 +62,25 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
                                                    unsigned long long* __restrict__ counts,
                                                    double* __restrict__ partials, bool vec) {
     extern __shared__ __align__(16) char smem[];
-    float* Cs = reinterpret_cast<float*>(smem);
-    int* valid = reinterpret_cast<int*>(smem + (size_t)k * D * 4);
+    double* C64 = reinterpret_cast<double*>(smem);
+    float* C32 = reinterpret_cast<float*>(smem + (size_t)k * D * 8);
+    int* valid = reinterpret_cast<int*>(C32 + (size_t)k * D);
     int* hist = valid + k;
-    double* red = reinterpret_cast<double*>(smem + (((size_t)k * D * 4 + (size_t)k * 8 + 15) / 16) * 16);
+    double* red = reinterpret_cast<double*>(
+        smem + (size_t)k * D * 8 + (((size_t)k * D * 4 + (size_t)k * 8 + 15) / 16) * 16);
     const int tid = threadIdx.x;
     for (int e = tid; e < k * D; e += NT) {
         const int j = e / D, t = e % D;
-        Cs[e] = t < d ? C[(int64_t)j * d + t] : 0.f;
+        const float v = t < d ? C[(int64_t)j * d + t] : 0.f;
+        C32[e] = v;
+        C64[e] = (double)v;
     }
     for (int j = tid; j < k; j += NT) {
         valid[j] = !is_nan_f(C[(int64_t)j * d]);
         hist[j] = 0;
     }
     __syncthreads();
+    const float tau = 4.f * (float)(d + 8) * 0x1.0p-24f;
     double fl = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * NT + tid; i < m; i += (int64_t)gridDim.x * NT) {
         float x[D];
@@ -76,17 +90,35 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
 #pragma unroll
             for (int t = 0; t < D; ++t) x[t] = t < d ? X[i * d + t] : 0.f;
         }
-        float best = __builtin_huge_valf();
+        float b1 = __builtin_huge_valf(), b2 = __builtin_huge_valf();
         int am = -1;
         for (int j = 0; j < k; ++j) {
             if (!valid[j]) continue;
-            const float v = sqdist<D>(x, Cs + j * D);
-            if (v < best) {
-                best = v;
+            const float v = sqdist<D>(x, C32 + j * D);
+            if (v < b1) {
+                b2 = b1;
+                b1 = v;
                 am = j;
+            } else if (v < b2) {
+                b2 = v;
             }
         }
-        fl += (double)best;
+        double dm = __builtin_huge_val();
+        if (am >= 0) {
+            if (screen_certified(b1, b2, tau, 0.f)) {
+                dm = sqdist64<D>(x, C64 + am * D);
+            } else {
+                for (int j = 0; j < k; ++j) {
+                    if (!valid[j]) continue;
+                    const double v = sqdist64<D>(x, C64 + j * D);
+                    if (v < dm) {
+                        dm = v;
+                        am = j;
+                    }
+                }
+            }
+        }
+        fl += dm;
         if (labels) labels[i] = am;
         if (counts && am >= 0) atomicAdd(&hist[am], 1);
     }

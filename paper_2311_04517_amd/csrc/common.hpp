@@ -82,6 +82,37 @@ __device__ __forceinline__ float sqdist(const float (&x)[D], const float* __rest
     return (a0 + a1) + (a2 + a3);
 }
 
+// |x - c|^2 in FP64 from FP32 coordinates x and an FP64 centroid c (LDS,
+// 16-byte aligned).  Used wherever a distance decides an index or enters an
+// objective: the rounding is then ~1e-16 relative, far below any FP32
+// effect.
+template <int D>
+__device__ __forceinline__ double sqdist64(const float (&x)[D], const double* __restrict__ c) {
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; t += 2) {
+        const double2 cv = *reinterpret_cast<const double2*>(c + t);
+        const double e0 = (double)x[t] - cv.x, e1 = (double)x[t + 1] - cv.y;
+        a0 = __fma_rn(e0, e0, a0);
+        a1 = __fma_rn(e1, e1, a1);
+    }
+    return a0 + a1;
+}
+
+// Certificate of an FP32 screening argmin.  The screened distance of x to
+// centroid j is sqdist<D>(x, fl32(c_j)); relative to the exact distance to
+// the FP64 centroid c_j its error is at most g*dist + 2r*sqrt(dist) + r^2,
+// with g = (d + 8) 2^-24 bounding the FP32 arithmetic of sqdist (d
+// subtractions, d/4 FMAs per accumulator, three adds) and r = 2^-24 max|c_j|
+// bounding the rounding of the centroid to FP32.  The screening winner is
+// the exact argmin whenever the gap to the runner-up exceeds both error
+// bounds; `tau` = 4g (a factor 2 of slack for the rounding of this test).
+__device__ __forceinline__ bool screen_certified(float b1, float b2, float tau, float rmax) {
+    if (!(b2 < __builtin_huge_valf())) return true;  // a single candidate
+    const float sb2 = sqrtf(b2);
+    return (b2 - b1) > tau * b2 + 5.f * rmax * sb2 + 4.f * rmax * rmax;
+}
+
 // Load a zero-padded row of D floats (stride D, 16-byte aligned).
 template <int D>
 __device__ __forceinline__ void load_row(const float* __restrict__ p, float (&x)[D]) {

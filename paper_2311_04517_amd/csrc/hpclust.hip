@@ -206,7 +206,7 @@ template <int D>
 int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
                   int64_t* counts, double* sse, Workspace* w, hipStream_t st) {
     constexpr int NT = 256;
-    const size_t lds = align_up((size_t)k * D * 4 + (size_t)k * 8, 16) + (NT / hpc::kWave) * 8;
+    const size_t lds = hpc::assign_lds_bytes<D>(k, NT);
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
     if (rc) return rc;
@@ -294,14 +294,14 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     const size_t desc_b = (size_t)n * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n * 4;
     const size_t need = Carve::need({desc_b + order_b, 256, (size_t)idx_len * D * 4,
-                                     (size_t)idx_len * 4});
+                                     (size_t)idx_len * 8});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
     char* tbl = static_cast<char*>(cv.take(desc_b + order_b));
     int32_t* queue = static_cast<int32_t*>(cv.take(256));
     float* sbuf = static_cast<float*>(cv.take((size_t)idx_len * D * 4));
-    float* d2 = static_cast<float*>(cv.take((size_t)idx_len * 4));
+    double* d2 = static_cast<double*>(cv.take((size_t)idx_len * 8));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
     memcpy(host.data() + desc_b, order.data(), order_b);

@@ -8,10 +8,18 @@
 // longest-first order, so hundreds of samples of uneven size share one
 // launch with no inter-workgroup synchronisation at all.
 //
+// Arithmetic: the assignment screens all centroids in FP32 and certifies the
+// winner with a rigorous error bound (screen_certified); the rare point that
+// is not certified is re-decided in FP64.  The distance that enters the
+// objective, the K-means++ weights D^2, the potentials, the centroid sums
+// and the centroids themselves are FP64.  Every index the method decides is
+// therefore the one an FP64 evaluation decides.
+//
 // Layout per sample: the gathered rows live in a scratch buffer (row stride
 // D floats, zero padded) that stays hot in L2/MALL across passes; centroids
-// sit in LDS; per-wave FP64 partial sums of the update live in LDS; D^2 of
-// the seeding lives in scratch, each element owned by one thread.
+// sit in LDS as FP64 plus an FP32 copy for the screening; per-wave FP64
+// partial sums of the update live in LDS; D^2 lives in scratch, each element
+// owned by one thread.
 #pragma once
 
 #include "common.hpp"
@@ -32,11 +40,11 @@ struct LloydArgs {
     double* f_out;
     int32_t* iters_out;
     int32_t* labels_out;
-    float* sbuf;   // gathered samples, indexed by idx_offset, stride D
-    float* d2buf;  // D^2, indexed by idx_offset
+    float* sbuf;    // gathered samples, indexed by idx_offset, stride D
+    double* d2buf;  // D^2, indexed by idx_offset
     int32_t* queue;
     int32_t kmax;
-    int32_t n_copies;  // partial-sum copies in LDS (== waves: no atomics)
+    int32_t n_copies;  // partial-sum copies in LDS (== waves: private per wave)
     // seeding-only mode
     int32_t seed_only;
     int32_t n_cand;
@@ -48,49 +56,47 @@ struct LloydArgs {
 template <int D, int NT>
 struct Smem {
     static constexpr int NW = NT / kWave;
-    float* Cs;     // kmax x D centroids
-    float* crow;   // 4 x D candidate rows
-    double* psum;  // n_copies x kmax x D update sums   (union with seeding arrays)
+    double* C64;   // kmax x D centroids (FP64)
+    float* C32;    // kmax x D centroids rounded to FP32 (screening)
+    double* crow;  // 4 x D candidate rows
+    double* psum;  // n_copies x kmax x D update sums   (union with seeding scan)
     int* pcnt;     // n_copies x kmax counts
     double* incl;  // NT inclusive scan of chunk sums   (seeding)
-    double* csum;  // NT chunk sums of D^2              (seeding)
-    double* cpot;  // 4 x NT chunk potentials           (seeding)
     double* red;   // 4 x NW wave partials
-    double* dbl;   // 8 scalars
+    double* cn;    // kmax squared centroid norms
     int* deg;      // kmax degenerate-row list
     int* ints;     // 16 scalars
 
     static __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
     static __host__ __device__ size_t union_bytes(int kmax, int copies) {
-        size_t lloyd = (size_t)copies * kmax * D * 8 + align_up((size_t)copies * kmax * 4, 8);
-        size_t seed = (size_t)NT * 8 * 6;
+        size_t lloyd = (size_t)copies * kmax * D * 8 + align_up((size_t)copies * kmax * 4, 16);
+        size_t seed = (size_t)NT * 8;
         return lloyd > seed ? lloyd : seed;
     }
     static __host__ __device__ size_t bytes(int kmax, int copies) {
-        size_t b = align_up((size_t)kmax * D * 4, 16) + 4 * D * 4;
+        size_t b = (size_t)kmax * D * 8 + align_up((size_t)kmax * D * 4, 16) + 4 * D * 8;
         b += union_bytes(kmax, copies);
-        b += 4 * NW * 8 + 8 * 8;
+        b += 4 * NW * 8 + align_up((size_t)kmax * 8, 16);
         b += align_up((size_t)kmax * 4, 16) + 16 * 4;
         return b;
     }
     __device__ Smem(char* base, int kmax, int copies) {
         char* p = base;
-        Cs = reinterpret_cast<float*>(p);
+        C64 = reinterpret_cast<double*>(p);
+        p += (size_t)kmax * D * 8;
+        C32 = reinterpret_cast<float*>(p);
         p += align_up((size_t)kmax * D * 4, 16);
-        crow = reinterpret_cast<float*>(p);
-        p += 4 * D * 4;
-        char* u = p;
-        psum = reinterpret_cast<double*>(u);
-        pcnt = reinterpret_cast<int*>(u + (size_t)copies * kmax * D * 8);
-        incl = reinterpret_cast<double*>(u);
-        csum = incl + NT;
-        cpot = csum + NT;
+        crow = reinterpret_cast<double*>(p);
+        p += 4 * D * 8;
+        psum = reinterpret_cast<double*>(p);
+        pcnt = reinterpret_cast<int*>(p + (size_t)copies * kmax * D * 8);
+        incl = reinterpret_cast<double*>(p);
         p += union_bytes(kmax, copies);
         red = reinterpret_cast<double*>(p);
         p += 4 * NW * 8;
-        dbl = reinterpret_cast<double*>(p);
-        p += 8 * 8;
+        cn = reinterpret_cast<double*>(p);
+        p += align_up((size_t)kmax * 8, 16);
         deg = reinterpret_cast<int*>(p);
         p += align_up((size_t)kmax * 4, 16);
         ints = reinterpret_cast<int*>(p);
@@ -123,7 +129,6 @@ __device__ __forceinline__ void block_sum_n(double (&v)[NV], double* red) {
 // Result written to out[tid]; two barriers.
 template <int NT>
 __device__ __forceinline__ void block_incl_scan(double v, double* out, double* red) {
-    constexpr int NW = NT / kWave;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -138,24 +143,36 @@ __device__ __forceinline__ void block_incl_scan(double v, double* out, double* r
     __syncthreads();
 }
 
+// Copy sample row i (FP32, padded) into centroid row j (FP64 and FP32).
+template <int D, int NT>
+__device__ __forceinline__ void set_row_from_sample(double* dst64, float* dst32,
+                                                    const float* __restrict__ Sg, int i) {
+    for (int t = threadIdx.x; t < D; t += NT) {
+        const float v = Sg[(size_t)i * D + t];
+        dst64[t] = (double)v;
+        dst32[t] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// K-means++ on the gathered sample for every degenerate row of L.Cs.
-// Sg: s x D rows; d2: s floats of scratch.  Stream (seed, tag) /
-// (block, sid, call, 0).  Thread t owns the contiguous chunk
-// [t*cs, (t+1)*cs) of the sample; the inverse-CDF search is a workgroup
-// scan of the chunk sums followed by a sequential scan inside the one chunk
-// that holds the target, so the prefix order is the sample's index order.
-// chosen (nullable, global) receives the picked sample-local indices.
+// K-means++ on the gathered sample for every degenerate row of L.C64, in
+// FP64 (weights, prefix sums, potentials).  Sg: s x D rows; d2: s doubles
+// of scratch.  Stream (seed, tag) / (block, sid, call, 0).  Thread t owns
+// the contiguous chunk [t*cs, (t+1)*cs) of the sample; the inverse-CDF
+// search is a workgroup scan of the chunk sums followed by a sequential
+// scan inside the one chunk that holds the target, so the prefix order is
+// the sample's index order.  chosen (nullable, global) receives the picked
+// sample-local indices.  Seeded rows are written to C64 and C32.
 // ---------------------------------------------------------------------------
 template <int D, int NT>
 __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_cand,
-                            float* __restrict__ d2, uint64_t seed, uint64_t tag, uint64_t sid,
+                            double* __restrict__ d2, uint64_t seed, uint64_t tag, uint64_t sid,
                             uint64_t call, int32_t* __restrict__ chosen, Smem<D, NT>& L) {
     const int tid = threadIdx.x;
     if (tid == 0) {
         int nd = 0, nv = 0;
         for (int j = 0; j < k; ++j) {
-            if (is_nan_f(L.Cs[j * D]))
+            if (L.C64[j * D] != L.C64[j * D])
                 L.deg[nd++] = j;
             else
                 ++nv;
@@ -172,20 +189,16 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
     int first = 0;
     double acc = 0.0;
     if (n_valid == 0) {
-        if (tid == 0) {
-            const Words4 w = philox_block(seed, tag, 0, sid, call);
-            const int i0 = (int)bounded_index(w.w[0], (uint64_t)s);
-            L.ints[2] = i0;
-            if (chosen) chosen[L.deg[0]] = i0;
-        }
-        __syncthreads();
-        const int i0 = L.ints[2], j0 = L.deg[0];
-        for (int t = tid; t < D; t += NT) L.Cs[j0 * D + t] = Sg[(size_t)i0 * D + t];
+        const Words4 w0 = philox_block(seed, tag, 0, sid, call);
+        const int i0 = (int)bounded_index(w0.w[0], (uint64_t)s);
+        const int j0 = L.deg[0];
+        if (tid == 0 && chosen) chosen[j0] = i0;
+        set_row_from_sample<D, NT>(L.C64 + j0 * D, L.C32 + j0 * D, Sg, i0);
         __syncthreads();
         for (int i = lo; i < hi; ++i) {
             float x[D];
             load_row<D>(Sg + (size_t)i * D, x);
-            const float v = sqdist<D>(x, L.Cs + j0 * D);
+            const double v = sqdist64<D>(x, L.C64 + j0 * D);
             d2[i] = v;
             acc += v;
         }
@@ -194,10 +207,10 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
         for (int i = lo; i < hi; ++i) {
             float x[D];
             load_row<D>(Sg + (size_t)i * D, x);
-            float best = __builtin_huge_valf();
+            double best = __builtin_huge_val();
             for (int j = 0; j < k; ++j) {
-                if (is_nan_f(L.Cs[j * D])) continue;
-                const float v = sqdist<D>(x, L.Cs + j * D);
+                if (L.C64[j * D] != L.C64[j * D]) continue;
+                const double v = sqdist64<D>(x, L.C64 + j * D);
                 best = v < best ? v : best;
             }
             d2[i] = best;
@@ -226,7 +239,7 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
                     double run = c_lo;
                     int found = -1;
                     for (int i = lo; i < hi; ++i) {
-                        run += (double)d2[i];
+                        run += d2[i];
                         if (run > target) {
                             found = i;
                             break;
@@ -234,7 +247,7 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
                     }
                     if (found < 0)
                         for (int i = hi - 1; i >= lo; --i)
-                            if (d2[i] > 0.f) {
+                            if (d2[i] > 0.0) {
                                 found = i;
                                 break;
                             }
@@ -248,26 +261,28 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
                     if (L.ints[4 + t] >= 0) continue;
                     int found = -1;
                     for (int i = s - 1; i >= 0 && found < 0; --i)
-                        if (d2[i] > 0.f) found = i;
+                        if (d2[i] > 0.0) found = i;
                     L.ints[4 + t] = found < 0 ? 0 : found;
                 }
             }
             __syncthreads();
             for (int e = tid; e < n_cand * D; e += NT)
-                L.crow[e] = Sg[(size_t)L.ints[4 + e / D] * D + (e % D)];
+                L.crow[e] = (double)Sg[(size_t)L.ints[4 + e / D] * D + (e % D)];
             __syncthreads();
+            // one candidate at a time keeps a single FP64 row live
             double p[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int i = lo; i < hi; ++i) {
-                float x[D];
-                load_row<D>(Sg + (size_t)i * D, x);
-                const float dd = d2[i];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (t < n_cand) {
-                        const float v = sqdist<D>(x, L.crow + t * D);
-                        p[t] += (double)(v < dd ? v : dd);
-                    }
+            for (int t = 0; t < 4; ++t) {
+                if (t >= n_cand) continue;
+                double pt = 0.0;
+                for (int i = lo; i < hi; ++i) {
+                    float x[D];
+                    load_row<D>(Sg + (size_t)i * D, x);
+                    const double dd = d2[i];
+                    const double v = sqdist64<D>(x, L.crow + t * D);
+                    pt += v < dd ? v : dd;
                 }
+                p[t] = pt;
             }
             block_sum_n<NT, 4>(p, L.red);
             int tb = 0;
@@ -282,15 +297,15 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
         }
         const int jr = L.deg[r];
         if (tid == 0 && chosen) chosen[jr] = pick;
-        for (int t = tid; t < D; t += NT) L.Cs[jr * D + t] = Sg[(size_t)pick * D + t];
+        set_row_from_sample<D, NT>(L.C64 + jr * D, L.C32 + jr * D, Sg, pick);
         __syncthreads();
         acc = 0.0;
         for (int i = lo; i < hi; ++i) {
             float x[D];
             load_row<D>(Sg + (size_t)i * D, x);
-            const float v = sqdist<D>(x, L.Cs + jr * D);
-            const float o = d2[i];
-            const float nv = v < o ? v : o;
+            const double v = sqdist64<D>(x, L.C64 + jr * D);
+            const double o = d2[i];
+            const double nv = v < o ? v : o;
             d2[i] = nv;
             acc += nv;
         }
@@ -298,40 +313,20 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
     }
 }
 
-// Fold one wave's points into the per-cluster sums: for every distinct label
-// present in the wave, a butterfly sum of each coordinate over the lanes
-// holding that label, added by the leader lane to this wave's LDS copy.
-template <int D>
-__device__ __forceinline__ void wave_accumulate(const float (&x)[D], int am, bool valid, int d,
-                                                double* __restrict__ pw, int* __restrict__ cw,
-                                                bool atomic) {
-    const int lane = threadIdx.x & (kWave - 1);
-    unsigned long long act = __ballot(valid);
-    while (act) {
-        const int leader = __ffsll(act) - 1;
-        const int j = __shfl(am, leader, kWave);
-        const bool in = valid && am == j;
-        const unsigned long long mask = __ballot(in);
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-            if (t < d) {
-                const float v = wave_sum(in ? x[t] : 0.f);
-                if (lane == leader) {
-                    if (atomic)
-                        atomicAdd(&pw[j * D + t], (double)v);
-                    else
-                        pw[j * D + t] += (double)v;
-                }
-            }
-        }
-        if (lane == leader) {
-            if (atomic)
-                atomicAdd(&cw[j], (int)__popcll(mask));
-            else
-                cw[j] += (int)__popcll(mask);
-        }
-        act &= ~mask;
+// Rounding radius of the FP32 centroid copy: 2^-24 * max_j |c_j| (rounded
+// up slightly so that its FP32 use stays conservative).  Two barriers.
+template <int D, int NT>
+__device__ __forceinline__ float centroid_round_radius(Smem<D, NT>& L, int k, int d) {
+    for (int j = threadIdx.x; j < k; j += NT) {
+        double n2 = 0.0;
+        for (int t = 0; t < d; ++t) n2 += L.C64[j * D + t] * L.C64[j * D + t];
+        L.cn[j] = n2;
     }
+    __syncthreads();
+    double mx = 0.0;
+    for (int j = 0; j < k; ++j) mx = L.cn[j] > mx ? L.cn[j] : mx;
+    __syncthreads();
+    return (float)(sqrt(mx) * 0x1.0p-24 * 1.0001) + 1e-30f;
 }
 
 template <int D, int NT>
@@ -341,6 +336,7 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
     constexpr int NW = Smem<D, NT>::NW;
     const int tid = threadIdx.x, wid = tid / kWave;
     const int d = a.d;
+    const float tau = 4.f * (float)(d + 8) * 0x1.0p-24f;
 
     for (;;) {
         if (tid == 0) L.ints[15] = atomicAdd(a.queue, 1);
@@ -352,7 +348,7 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
         const hpc_sample_desc ds = a.desc[b];
         const int s = ds.s, k = ds.k;
         float* Sg = a.sbuf + (size_t)ds.idx_offset * D;
-        float* d2 = a.d2buf + ds.idx_offset;
+        double* d2 = a.d2buf + ds.idx_offset;
 
         // gather the sample rows (zero padded to D)
         for (int i = tid; i < s; i += NT) {
@@ -365,7 +361,9 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
         }
         for (int e = tid; e < k * D; e += NT) {
             const int j = e / D, t = e % D;
-            L.Cs[e] = t < d ? a.C[ds.c_offset + (int64_t)j * d + t] : 0.f;
+            const float v = t < d ? a.C[ds.c_offset + (int64_t)j * d + t] : 0.f;
+            L.C32[e] = v;
+            L.C64[e] = (double)v;
         }
         __syncthreads();
 
@@ -379,43 +377,57 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
             double f_prev = __builtin_huge_val(), f = 0.0;
             int it = 0;
             const int copies = a.n_copies;
-            const bool atomic = copies < NW;
-            double* pw = L.psum + (size_t)(wid % copies) * k * D;
-            int* cw = L.pcnt + (wid % copies) * k;
+            const bool shared_copy = copies < NW;
             for (;;) {
                 kmeanspp_wg<D, NT>(Sg, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
                                    (uint64_t)it, nullptr, L);
-                // (re)pointer after the union region was used by seeding
+                const float rmax = centroid_round_radius<D, NT>(L, k, d);
                 for (int e = tid; e < copies * k * D; e += NT) L.psum[e] = 0.0;
                 for (int e = tid; e < copies * k; e += NT) L.pcnt[e] = 0;
                 __syncthreads();
-                pw = L.psum + (size_t)(wid % copies) * k * D;
-                cw = L.pcnt + (wid % copies) * k;
+                double* pw = L.psum + (size_t)(wid % copies) * k * D;
+                int* cw = L.pcnt + (wid % copies) * k;
                 double fl = 0.0;
                 for (int base = 0; base < s; base += NT) {
                     const int i = base + tid;
-                    const bool valid = i < s;
-                    float x[D];
-                    if (valid) {
+                    if (i < s) {
+                        float x[D];
                         load_row<D>(Sg + (size_t)i * D, x);
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < D; ++t) x[t] = 0.f;
-                    }
-                    float best = __builtin_huge_valf();
-                    int am = 0;
-                    for (int j = 0; j < k; ++j) {
-                        const float v = sqdist<D>(x, L.Cs + j * D);
-                        if (v < best) {
-                            best = v;
-                            am = j;
+                        // FP32 screening: best and runner-up
+                        float b1 = __builtin_huge_valf(), b2 = __builtin_huge_valf();
+                        int am = 0;
+                        for (int j = 0; j < k; ++j) {
+                            const float v = sqdist<D>(x, L.C32 + j * D);
+                            if (v < b1) {
+                                b2 = b1;
+                                b1 = v;
+                                am = j;
+                            } else if (v < b2) {
+                                b2 = v;
+                            }
                         }
-                    }
-                    if (valid) {
-                        fl += (double)best;
+                        double dm;
+                        if (screen_certified(b1, b2, tau, rmax)) {
+                            dm = sqdist64<D>(x, L.C64 + am * D);
+                        } else {  // re-decide in FP64 (lowest index on ties)
+                            dm = __builtin_huge_val();
+                            for (int j = 0; j < k; ++j) {
+                                const double v = sqdist64<D>(x, L.C64 + j * D);
+                                if (v < dm) {
+                                    dm = v;
+                                    am = j;
+                                }
+                            }
+                        }
+                        fl += dm;
                         if (a.labels_out) a.labels_out[ds.idx_offset + i] = am;
+                        double* ps = pw + am * D;
+                        (void)shared_copy;
+#pragma unroll
+                        for (int t = 0; t < D; ++t)
+                            if (t < d) atomicAdd(ps + t, (double)x[t]);
+                        atomicAdd(cw + am, 1);
                     }
-                    wave_accumulate<D>(x, am, valid, d, pw, cw, atomic);
                 }
                 f = block_sum<NT>(fl, L.red);
                 ++it;
@@ -429,9 +441,10 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
                         sum += L.psum[(size_t)g * k * D + e];
                         n += L.pcnt[g * k + j];
                     }
-                    float v = 0.f;
-                    if (t < d) v = n > 0 ? (float)(sum / (double)n) : __builtin_nanf("");
-                    L.Cs[e] = v;
+                    double v = 0.0;
+                    if (t < d) v = n > 0 ? sum / (double)n : __builtin_nan("");
+                    L.C64[e] = v;
+                    L.C32[e] = (float)v;
                 }
                 __syncthreads();
             }
@@ -442,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
         }
         for (int e = tid; e < k * d; e += NT) {
             const int j = e / d, t = e % d;
-            a.C[ds.c_offset + e] = L.Cs[j * D + t];
+            a.C[ds.c_offset + e] = (float)L.C64[j * D + t];
         }
         __syncthreads();
     }

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import synthetic
-from tests.tolerances import (F_REL, SSE_REL, TIE_REL, assert_centroids, assert_labels,
+from tests.tolerances import (CLEAN_MARGIN, F_REL, SSE_REL, assert_centroids, assert_labels,
                               diag_clean, rel)
 
 pytestmark = pytest.mark.gpu
@@ -113,12 +113,12 @@ def test_seed_kmeanspp_bit_exact(hp, orc, d, s, k):
     clean = 0
     for call in range(6):
         Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, s, k, 5, 1, call)
-        if g["min_draw_margin"] < 1e-5 or g["min_cand_margin"] < 1e-5:
+        if g["min_draw_margin"] < CLEAN_MARGIN or g["min_cand_margin"] < CLEAN_MARGIN:
             continue
         clean += 1
         assert np.array_equal(chg, cho), (call, chg, cho)
         assert np.array_equal(Cg.astype(np.float64), Co)
-    assert clean >= 3
+    assert clean >= 5
 
 
 def test_seed_kmeanspp_partial_and_candidates(hp, orc):
@@ -128,7 +128,7 @@ def test_seed_kmeanspp_partial_and_candidates(hp, orc):
         Cin = Xn[rng.integers(0, 20_000, size=9)].astype(np.float64)
         Cin[[1, 4, 8]] = np.nan
         Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 1500, 9, 11, 2, n_cand, Cin, n_cand)
-        if g["min_draw_margin"] < 1e-5 or g["min_cand_margin"] < 1e-5:
+        if g["min_draw_margin"] < CLEAN_MARGIN or g["min_cand_margin"] < CLEAN_MARGIN:
             continue
         assert np.array_equal(chg, cho)
         assert (chg[[0, 2, 3, 5, 6, 7]] == -1).all()
@@ -146,7 +146,7 @@ def test_seed_zero_weight_and_duplicates(hp, orc):
     # k = s distinct points: every point chosen once
     Xn, Xg = _mix(1000, 3, 2, seed=3)
     Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 64, 64, 2, 0, 0)
-    if g["min_draw_margin"] >= 1e-5 and g["min_cand_margin"] >= 1e-5:
+    if g["min_draw_margin"] >= CLEAN_MARGIN and g["min_cand_margin"] >= CLEAN_MARGIN:
         assert np.array_equal(chg, cho)
 
 
@@ -169,10 +169,10 @@ def test_lloyd_teacher_forced_two_passes(hp, orc, d, s, k):
     desc, _, _ = hp.make_desc([s], [k], seed=3, sample_id=[0], d=d)
     Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0, max_iter=2, rel_tol=0.0)
     assert itg[0] == ro.iters == 2
-    if ro.diag["n_label_ties"] == 0:
-        assert_centroids(Cg.reshape(k, d), ro.C, Xn[idx])
-        assert rel(fg[0], ro.f) <= F_REL
-    assert_labels(lg, ro.labels, ro.margins)
+    assert diag_clean(ro.diag)
+    assert_centroids(Cg.reshape(k, d), ro.C, Xn[idx])
+    assert rel(fg[0], ro.f) <= F_REL
+    assert np.array_equal(lg, ro.labels)
 
 
 @pytest.mark.parametrize("d,s,k,mseed", [(8, 2000, 10, 0), (32, 10_000, 25, 1), (12, 3001, 6, 2)])
@@ -194,7 +194,7 @@ def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed):
         assert rel(fg[0], ro.f) <= F_REL
         assert_centroids(Cg.reshape(k, d), ro.C, Xn[idx])
         assert_labels(lg, ro.labels, ro.margins)
-    assert clean >= 2, "too few clean seeds"
+    assert clean >= 5, "too few clean seeds"
 
 
 def test_lloyd_reseeds_emptied_cluster(hp, orc):
@@ -316,29 +316,49 @@ def test_keep_and_select_best(hp):
 # ---------------------------------------------------------------- worker loop
 def test_worker_loop_plain_small_config(hp, orc):
     """The plain small workload (m = 50,000, d = 8, k = 10, s = 2,000, 8
-    samples, K-means++, max 300 passes, tol 1e-4, then full assignment)."""
+    samples, K-means++, max 300 passes, tol 1e-4, then full assignment).
+    Every sample is compared with the oracle started from the GPU's own
+    incumbent (the boundary stores incumbents in FP32); the whole loop is
+    also compared end to end with the oracle's loop."""
     from paper_2311_04517_amd import driver
 
     mx = synthetic.plain_small()
     Xn = mx.X.numpy()
     Xg = mx.X.cuda()
-    clean = 0
-    for seed in range(4):
-        wo = orc.worker_loop(Xn, s=2000, k=10, n_samples=8, seed=seed)
-        wg = driver.worker_loop(Xg, s=2000, k=10, n_samples=8, seed=seed)
-        torch.cuda.synchronize()
-        fo = wo["f_samples"]
-        keep_margin = min(abs(fo[t] - fo[:t].min()) / fo[:t].min() for t in range(1, 8))
-        if not diag_clean(wo["diag"]) or keep_margin < 1e-5:
-            continue
-        clean += 1
-        assert np.array_equal(wg.iters.cpu().numpy(), wo["iters"])
-        for t in range(8):
-            assert rel(wg.f_samples[t].item(), fo[t]) <= F_REL
-        assert_centroids(wg.C.cpu().numpy(), wo["C"], Xn)
-        assert rel(wg.sse.item(), wo["sse"]) <= SSE_REL
-        full = orc.assign_sse(Xn, wo["C"], want_margins=True)
-        assert_labels(wg.labels.cpu().numpy(), wo["labels"], full["margins"])
-        assert np.array_equal(wg.counts.cpu().numpy(), np.bincount(wg.labels.cpu().numpy(),
-                                                                   minlength=10))
-    assert clean >= 1
+    m, d, s, k, n = 50_000, 8, 2000, 10, 8
+    e2e_ok = 0
+    for seed in range(3):
+        C_w = torch.full((k, d), float("nan"), device="cuda")
+        f_hat = torch.full((1,), float("inf"), dtype=torch.float64, device="cuda")
+        C = torch.empty_like(C_w)
+        idx = torch.empty(s, dtype=torch.int64, device="cuda")
+        f_s = torch.empty(n, dtype=torch.float64, device="cuda")
+        it_s = torch.empty(n, dtype=torch.int32, device="cuda")
+        for t in range(n):
+            hp.draw_sample(m, s, seed, t, out=idx)
+            C.copy_(C_w)
+            start = C_w.double().cpu().numpy()
+            desc, _, _ = hp.make_desc([s], [k], seed=seed, sample_id=[t], d=d)
+            hp.lloyd_batch(Xg, idx, desc, C, f_out=f_s[t:t + 1], iters_out=it_s[t:t + 1])
+            ro = orc.lloyd(Xn, idx.cpu().numpy(), k, start, seed=seed, sample_id=t)
+            assert diag_clean(ro.diag)
+            assert it_s[t].item() == ro.iters
+            assert rel(f_s[t].item(), ro.f) <= F_REL
+            assert_centroids(C.cpu().numpy(), ro.C, Xn[idx.cpu().numpy()])
+            prev = f_hat.item()
+            hp.keep_best(C, f_s[t:t + 1], C_w, f_hat, k, d)
+            assert f_hat.item() == min(prev, f_s[t].item())
+        lab, cnt, sse = hp.assign_sse(Xg, C_w)
+        full = orc.assign_sse(Xn, C_w.double().cpu().numpy(), want_margins=True)
+        assert np.array_equal(lab.cpu().numpy(), full["labels"])
+        assert rel(sse.item(), full["sse"]) <= SSE_REL
+        assert np.array_equal(cnt.cpu().numpy(), full["counts"])
+        # end to end, the driver against the oracle's own loop
+        wo = orc.worker_loop(Xn, s=s, k=k, n_samples=n, seed=seed)
+        wg = driver.worker_loop(Xg, s=s, k=k, n_samples=n, seed=seed)
+        if np.array_equal(wg.iters.cpu().numpy(), wo["iters"]):
+            e2e_ok += 1
+            assert rel(wg.sse.item(), wo["sse"]) <= SSE_REL
+            assert_centroids(wg.C.cpu().numpy(), wo["C"], Xn)
+            assert np.array_equal(wg.labels.cpu().numpy(), wo["labels"])
+    assert e2e_ok >= 2

@@ -1,30 +1,26 @@
-"""Parity tolerances between the gfx950 path (FP32 distances, FP64 sums)
-and the FP64 oracle.
+"""Parity tolerances between the gfx950 path and the FP64 oracle.
 
-TIE_REL        relative gap (d2 - d1)/d2 below which a point's assignment is
-               exempt from bit-exact comparison (stated by the build's
-               target: 1e-5).  An FP32 direct-difference distance over d
-               coordinates has relative error at most about (d + 3) * 2^-24
-               (4e-6 at d = 64), so outside the band the FP32 and FP64
-               argmins agree.
-DRAW_MARGIN    a K-means++ draw whose target lies closer than this fraction
-               of the total weight to a prefix-sum boundary may pick the
-               neighbouring index (FP32 D^2 vs FP64): same bound as above.
-CAND_MARGIN    candidates whose potentials differ by less than this relative
-               gap may be ranked differently.
-STOP_MARGIN    a stop decision whose relative improvement lies within this
-               absolute distance of rel_tol may fall the other way (the two
-               objectives each carry the relative error above).
+The GPU path stores data and returned centroids in FP32 but takes every
+decision the method makes -- nearest centroid, K-means++ draw, best
+candidate, stop test -- on FP64 values: FP32 screening with a rigorous
+error certificate, FP64 re-decision of uncertified points, FP64 D^2,
+potentials, sums, objectives and in-kernel centroids.  GPU and oracle FP64
+values then differ only by summation order (~1e-16 relative per term).
+
+CLEAN_MARGIN   a decision whose oracle margin is below this may differ from
+               the GPU's by summation-order noise; a run is "clean" when no
+               decision is that close (1e-10, far above s * 1e-16).
+TIE_REL        relative top-2 gap (d2 - d1)/d2 within which a label may
+               differ (the build target states 1e-5; the GPU meets far less).
 F_REL, SSE_REL relative tolerance on sample objectives and full SSE (1e-6).
 C_REL          centroid rows: |c_gpu - c_orc| <= C_REL * (|c_orc| + sigma_S),
-               sigma_S the RMS spread of the sample (1e-5).
+               sigma_S the RMS spread of the sample (1e-5); the GPU's
+               centroids are FP64 values rounded to FP32 (6e-8).
 """
 import numpy as np
 
+CLEAN_MARGIN = 1e-10
 TIE_REL = 1e-5
-DRAW_MARGIN = 1e-5
-CAND_MARGIN = 1e-5
-STOP_MARGIN = 1e-5
 F_REL = 1e-6
 SSE_REL = 1e-6
 C_REL = 1e-5
@@ -32,8 +28,8 @@ C_REL = 1e-5
 
 def diag_clean(g: dict) -> bool:
     """No decision of the run sat within rounding of its threshold."""
-    return (g["min_label_margin"] >= TIE_REL and g["min_draw_margin"] >= DRAW_MARGIN
-            and g["min_cand_margin"] >= CAND_MARGIN and g["min_stop_margin"] >= STOP_MARGIN)
+    return (g["min_label_margin"] >= CLEAN_MARGIN and g["min_draw_margin"] >= CLEAN_MARGIN
+            and g["min_cand_margin"] >= CLEAN_MARGIN and g["min_stop_margin"] >= CLEAN_MARGIN)
 
 
 def assert_labels(gpu, orc, margins, what="labels"):
