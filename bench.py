@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables it)")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
+                    help="MFMA type of the distance screening (decisions are FP64-exact)")
     return ap.parse_args()
 
 
@@ -77,6 +79,7 @@ def main():
     counts = torch.empty(k, dtype=torch.int64, device=dev)
     sse = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    prec = api.PREC_BF16_MFMA if args.precision == "bf16" else api.PREC_FP32
 
     ev = {name: [] for name in ("lloyd", "assign")}
 
@@ -89,12 +92,12 @@ def main():
         e1 = torch.cuda.Event(enable_timing=True)
         e2 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        f, it, _ = api.lloyd_batch(X, idx, desc, C)
+        f, it, _ = api.lloyd_batch(X, idx, desc, C, precision=prec)
         e1.record(stream)
         api.keep_best(C, f, C_inc, f_inc, k, d)
         Cb, fb, wb = api.select_best(C_inc, f_inc, k, d)
         e2.record(stream)
-        api.assign_sse(X, Cb, labels=labels, counts=counts, sse=sse)
+        api.assign_sse(X, Cb, labels=labels, counts=counts, sse=sse, precision=prec)
         e3 = torch.cuda.Event(enable_timing=True)
         e3.record(stream)
         if timed:
@@ -148,14 +151,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64" if args.precision == "fp32" else "bf16+f64",
         "data": "synthetic",
         "config": {"workload": "gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round",
                    "m": m, "d": d, "k": k, "s": s, "workers": W, "strategy": "competitive",
                    "passes_per_step": float(passes.mean())},
         "roofline": {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_lloyd_resident<32,256>",
+                     "kernel": f"k_lloyd_resident<32,256,{prec}>",
                      "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
                      "avg_launch_ms": t_lloyd * 1e3},
         "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "mfma_screen.hpp"
 
 namespace hpc {
 
@@ -40,87 +41,107 @@ __global__ void k_draw_batch(int64_t m, const hpc_sample_desc* __restrict__ desc
 
 // ---------------------------------------------------------------------------
 // Full assignment + objective (Section 3 final step; Eq. (1)).  HBM-bound
-// stream over the rows of X: each thread takes whole rows (grid-stride),
-// centroids are staged in LDS (FP32 for the screening, FP64 for the exact
-// distance; zero padded to D, degenerate rows flagged).  The FP32 screening
-// winner is certified (the centroids are exact in FP32 here, so only the
-// arithmetic bound applies) or re-decided in FP64; the objective adds the
-// FP64 distance to the chosen centroid.  Counts go to an LDS histogram; the
-// objective is an FP64 per-thread partial reduced per workgroup in fixed
-// order, then across workgroups by k_reduce_partials in fixed order.
+// stream over the rows of X in tiles of 16 rows per wave (grid-stride): the
+// nearest valid centroid is screened on MFMA (mfma_screen.hpp) and either
+// certified or re-decided in FP64; the objective adds the FP64 distance to
+// the chosen centroid.  Centroids live in LDS (FP64 rows, MFMA operands,
+// |c|^2 biases; degenerate rows never chosen).  Counts go to an LDS
+// histogram; the objective is an FP64 per-lane partial reduced per
+// workgroup in fixed order, then across workgroups by k_reduce_partials in
+// fixed order.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int PREC>
 __host__ __device__ inline size_t assign_lds_bytes(int k, int nt) {
-    return (size_t)k * D * 8 + (((size_t)k * D * 4 + (size_t)k * 8 + 15) / 16) * 16 +
-           (size_t)(nt / kWave) * 8;
+    const int nb = (k + 15) / 16;
+    size_t b = (((size_t)k * Lay<D>::CS * 8 + 15) / 16) * 16;
+    b += ((aop_bytes<D, PREC>(nb) + 15) / 16) * 16 + (size_t)nb * 64;
+    b += (((size_t)k * 8 + 15) / 16) * 16;  // valid + hist
+    b += (size_t)(nt / kWave) * 8 + 16;
+    return b;
 }
 
-template <int D, int NT>
+template <int D, int NT, int PREC>
 __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, int64_t m, int d,
                                                    const float* __restrict__ C, int k,
                                                    int32_t* __restrict__ labels,
                                                    unsigned long long* __restrict__ counts,
                                                    double* __restrict__ partials, bool vec) {
     extern __shared__ __align__(16) char smem[];
-    double* C64 = reinterpret_cast<double*>(smem);
-    float* C32 = reinterpret_cast<float*>(smem + (size_t)k * D * 8);
-    int* valid = reinterpret_cast<int*>(C32 + (size_t)k * D);
-    int* hist = valid + k;
-    double* red = reinterpret_cast<double*>(
-        smem + (size_t)k * D * 8 + (((size_t)k * D * 4 + (size_t)k * 8 + 15) / 16) * 16);
-    const int tid = threadIdx.x;
-    for (int e = tid; e < k * D; e += NT) {
-        const int j = e / D, t = e % D;
-        const float v = t < d ? C[(int64_t)j * d + t] : 0.f;
-        C32[e] = v;
-        C64[e] = (double)v;
+    constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
+    constexpr int NW = NT / kWave;
+    const int nblk = (k + 15) / 16;
+    char* p = smem;
+    double* C64 = reinterpret_cast<double*>(p);
+    p += (((size_t)k * CS * 8 + 15) / 16) * 16;
+    void* aop = p;
+    p += ((aop_bytes<D, PREC>(nblk) + 15) / 16) * 16;
+    float* nrm = reinterpret_cast<float*>(p);
+    p += (size_t)nblk * 64;
+    int* hist = reinterpret_cast<int*>(p);
+    int* flag = hist + k;
+    p += (((size_t)k * 8 + 15) / 16) * 16;
+    double* red = reinterpret_cast<double*>(p);
+    const int tid = threadIdx.x, wid = tid / kWave, lane = tid & 63, g = lane >> 4;
+    for (int e = tid; e < k * CS; e += NT) {
+        const int j = e / CS, t = e % CS;
+        C64[e] = t < d ? (double)C[(int64_t)j * d + t] : 0.0;
     }
-    for (int j = tid; j < k; j += NT) {
-        valid[j] = !is_nan_f(C[(int64_t)j * d]);
-        hist[j] = 0;
+    for (int j = tid; j < k; j += NT) hist[j] = 0;
+    if (tid == 0) {
+        int nv = 0;
+        double mx = 0.0;
+        for (int j = 0; j < k; ++j) {
+            const float c0 = C[(int64_t)j * d];
+            if (c0 != c0) continue;
+            ++nv;
+            double n2 = 0.0;
+            for (int t = 0; t < d; ++t) {
+                const double v = (double)C[(int64_t)j * d + t];
+                n2 = __fma_rn(v, v, n2);
+            }
+            mx = n2 > mx ? n2 : mx;
+        }
+        flag[0] = nv;
+        reinterpret_cast<double*>(red)[NW] = sqrt(mx);
     }
     __syncthreads();
-    const float tau = 4.f * (float)(d + 8) * 0x1.0p-24f;
+    build_operands<D, PREC, NT>(C64, k, d, nblk, aop, nrm);
+    __syncthreads();
+    const int n_valid = flag[0];
+    double alpha, beta;
+    screen_coeffs<PREC>(d, &alpha, &beta);
+    const double cmax = red[NW];
+    const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
     double fl = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NT + tid; i < m; i += (int64_t)gridDim.x * NT) {
-        float x[D];
-        if (vec) {
-            load_row<D>(X + i * D, x);
+    const int64_t n_tiles = (m + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * NW + wid; tile < n_tiles;
+         tile += (int64_t)gridDim.x * NW) {
+        const int64_t i = tile * 16 + (lane & 15);
+        const bool valid = i < m;
+        float xq[DL];
+        if (valid && vec) {
+            load_quarter<D>(X + i * D, g, xq);
         } else {
 #pragma unroll
-            for (int t = 0; t < D; ++t) x[t] = t < d ? X[i * d + t] : 0.f;
-        }
-        float b1 = __builtin_huge_valf(), b2 = __builtin_huge_valf();
-        int am = -1;
-        for (int j = 0; j < k; ++j) {
-            if (!valid[j]) continue;
-            const float v = sqdist<D>(x, C32 + j * D);
-            if (v < b1) {
-                b2 = b1;
-                b1 = v;
-                am = j;
-            } else if (v < b2) {
-                b2 = v;
+            for (int t = 0; t < DL; ++t) {
+                const int dim = g * DL + t;
+                xq[t] = (valid && dim < d) ? X[i * d + dim] : 0.f;
             }
         }
-        double dm = __builtin_huge_val();
-        if (am >= 0) {
-            if (screen_certified(b1, b2, tau, 0.f)) {
-                dm = sqdist64<D>(x, C64 + am * D);
-            } else {
-                for (int j = 0; j < k; ++j) {
-                    if (!valid[j]) continue;
-                    const double v = sqdist64<D>(x, C64 + j * D);
-                    if (v < dm) {
-                        dm = v;
-                        am = j;
-                    }
-                }
+        const Top2 t2 = screen_tile<D, PREC>(xq, aop, nrm, nblk);
+        const float xn = cert_norm(point_norm2<D>(xq));
+        const bool ok = certified(t2, xn, ea, eb) || !valid;
+        int am = redecide64<D>(xq, !ok, top2_suffices(t2, xn, ea, eb), t2.a1 < k ? t2.a1 : 0,
+                               t2.a2 < k ? t2.a2 : 0, C64, k);
+        if (valid) {
+            // this lane's share of the objective: FP64 distance to the choice
+            fl += n_valid > 0 ? quarter_part64<D>(xq, C64 + am * CS) : __builtin_huge_val();
+            if (n_valid == 0) am = -1;
+            if (g == 0) {
+                if (labels) labels[i] = am;
+                if (counts && am >= 0) atomicAdd(&hist[am], 1);
             }
         }
-        fl += dm;
-        if (labels) labels[i] = am;
-        if (counts && am >= 0) atomicAdd(&hist[am], 1);
     }
     const double tot = block_sum<NT>(fl, red);
     if (tid == 0) partials[blockIdx.x] = tot;

@@ -1,5 +1,5 @@
 // Device-side building blocks shared by the gfx950 kernels of the hot path:
-// the Philox4x64-10 counter generator, the FP32 squared distance, and
+// the Philox4x64-10 counter generator, the FP64 squared distance, and
 // deterministic wave/workgroup reductions.
 #pragma once
 
@@ -59,29 +59,6 @@ __device__ __forceinline__ double unit_double(uint64_t r) {
     return (double)(r >> 11) * 0x1.0p-53;
 }
 
-// ---------------------------------------------------------------------------
-// Squared distance |x - c|^2 in FP32 (Eq. (1)).  x lives in registers, c in
-// LDS or global memory (16-byte aligned, D floats, zero-padded beyond d).
-// Four interleaved accumulators with explicit FMAs: the rounding sequence is
-// fixed by this code, so every kernel that calls it on the same operands
-// gets bit-identical results.
-// ---------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ float sqdist(const float (&x)[D], const float* __restrict__ c) {
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll
-    for (int t = 0; t < D; t += 4) {
-        const float4 cv = *reinterpret_cast<const float4*>(c + t);
-        const float e0 = x[t] - cv.x, e1 = x[t + 1] - cv.y, e2 = x[t + 2] - cv.z,
-                    e3 = x[t + 3] - cv.w;
-        a0 = __fmaf_rn(e0, e0, a0);
-        a1 = __fmaf_rn(e1, e1, a1);
-        a2 = __fmaf_rn(e2, e2, a2);
-        a3 = __fmaf_rn(e3, e3, a3);
-    }
-    return (a0 + a1) + (a2 + a3);
-}
-
 // |x - c|^2 in FP64 from FP32 coordinates x and an FP64 centroid c (LDS,
 // 16-byte aligned).  Used wherever a distance decides an index or enters an
 // objective: the rounding is then ~1e-16 relative, far below any FP32
@@ -97,20 +74,6 @@ __device__ __forceinline__ double sqdist64(const float (&x)[D], const double* __
         a1 = __fma_rn(e1, e1, a1);
     }
     return a0 + a1;
-}
-
-// Certificate of an FP32 screening argmin.  The screened distance of x to
-// centroid j is sqdist<D>(x, fl32(c_j)); relative to the exact distance to
-// the FP64 centroid c_j its error is at most g*dist + 2r*sqrt(dist) + r^2,
-// with g = (d + 8) 2^-24 bounding the FP32 arithmetic of sqdist (d
-// subtractions, d/4 FMAs per accumulator, three adds) and r = 2^-24 max|c_j|
-// bounding the rounding of the centroid to FP32.  The screening winner is
-// the exact argmin whenever the gap to the runner-up exceeds both error
-// bounds; `tau` = 4g (a factor 2 of slack for the rounding of this test).
-__device__ __forceinline__ bool screen_certified(float b1, float b2, float tau, float rmax) {
-    if (!(b2 < __builtin_huge_valf())) return true;  // a single candidate
-    const float sb2 = sqrtf(b2);
-    return (b2 - b1) > tau * b2 + 5.f * rmax * sb2 + 4.f * rmax * rmax;
 }
 
 // Load a zero-padded row of D floats (stride D, 16-byte aligned).
@@ -160,5 +123,36 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 __device__ __forceinline__ bool is_nan_f(float v) { return v != v; }
+
+// ---------------------------------------------------------------------------
+// Exchange with lane l ^ 16 / l ^ 32 through the gfx950 row-swap
+// instructions (VALU, no LDS round trip).  v_permlane16_swap(a, a) leaves,
+// in every lane, the value of lane l ^ 16 in its first result for odd rows
+// of 16 and in its second result for even rows; v_permlane32_swap(a, a)
+// does the same for halves of 32 lanes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned xor16_u32(unsigned v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ unsigned xor32_u32(unsigned v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ float lane_xor(float v, int o) {
+    const unsigned u = __float_as_uint(v);
+    return __uint_as_float(o == 16 ? xor16_u32(u) : xor32_u32(u));
+}
+__device__ __forceinline__ int lane_xor(int v, int o) {
+    const unsigned u = (unsigned)v;
+    return (int)(o == 16 ? xor16_u32(u) : xor32_u32(u));
+}
+__device__ __forceinline__ double lane_xor(double v, int o) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+    const unsigned nlo = o == 16 ? xor16_u32(lo) : xor32_u32(lo);
+    const unsigned nhi = o == 16 ? xor16_u32(hi) : xor32_u32(hi);
+    return __longlong_as_double((long long)(((unsigned long long)nhi << 32) | nlo));
+}
 
 }  // namespace hpc

@@ -158,9 +158,9 @@ int max_dyn_lds(int* bytes) {
 // --------------------------------------------------------------------------
 // Resident Lloyd / seeding launch.
 // --------------------------------------------------------------------------
-template <int D>
+template <int D, int PREC>
 int launch_resident(hpc::LloydArgs a, int n_wg, hipStream_t st) {
-    using S = hpc::Smem<D, kNT>;
+    using S = hpc::Smem<D, kNT, PREC>;
     constexpr int NW = kNT / hpc::kWave;
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
@@ -175,7 +175,7 @@ int launch_resident(hpc::LloydArgs a, int n_wg, hipStream_t st) {
                     "k=%d with padded d=%d needs %zu bytes of LDS per workgroup (limit %d)",
                     a.kmax, D, lds, lds_max);
     a.n_copies = copies;
-    auto kern = hpc::k_lloyd_resident<D, kNT>;
+    auto kern = hpc::k_lloyd_resident<D, kNT, PREC>;
     if (lds > 64 * 1024)
         HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -191,28 +191,34 @@ int launch_resident(hpc::LloydArgs a, int n_wg, hipStream_t st) {
     return HPC_OK;
 }
 
-int dispatch_resident(int D, const hpc::LloydArgs& a, int n_wg, hipStream_t st) {
+int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, int n_wg, hipStream_t st) {
+    const bool bf = prec == HPC_PREC_BF16_MFMA;
     switch (D) {
-        case 8: return launch_resident<8>(a, n_wg, st);
-        case 16: return launch_resident<16>(a, n_wg, st);
-        case 32: return launch_resident<32>(a, n_wg, st);
-        case 64: return launch_resident<64>(a, n_wg, st);
-        case 128: return launch_resident<128>(a, n_wg, st);
+        case 8: return bf ? launch_resident<8, hpc::kPrecBF16>(a, n_wg, st)
+                          : launch_resident<8, hpc::kPrecF32>(a, n_wg, st);
+        case 16: return bf ? launch_resident<16, hpc::kPrecBF16>(a, n_wg, st)
+                           : launch_resident<16, hpc::kPrecF32>(a, n_wg, st);
+        case 32: return bf ? launch_resident<32, hpc::kPrecBF16>(a, n_wg, st)
+                           : launch_resident<32, hpc::kPrecF32>(a, n_wg, st);
+        case 64: return bf ? launch_resident<64, hpc::kPrecBF16>(a, n_wg, st)
+                           : launch_resident<64, hpc::kPrecF32>(a, n_wg, st);
+        case 128: return bf ? launch_resident<128, hpc::kPrecBF16>(a, n_wg, st)
+                            : launch_resident<128, hpc::kPrecF32>(a, n_wg, st);
     }
     return fail(HPC_ERR_UNSUPPORTED, "padded dimension %d", D);
 }
 
-template <int D>
+template <int D, int PREC>
 int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
                   int64_t* counts, double* sse, Workspace* w, hipStream_t st) {
     constexpr int NT = 256;
-    const size_t lds = hpc::assign_lds_bytes<D>(k, NT);
+    const size_t lds = hpc::assign_lds_bytes<D, PREC>(k, NT);
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
     if (rc) return rc;
     if (lds > (size_t)lds_max)
         return fail(HPC_ERR_UNSUPPORTED, "k=%d, padded d=%d: centroids exceed LDS", k, D);
-    auto kern = hpc::k_assign_sse<D, NT>;
+    auto kern = hpc::k_assign_sse<D, NT, PREC>;
     if (lds > 64 * 1024)
         HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -220,7 +226,7 @@ int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32
     HPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds));
     rc = device_cus(&cus);
     if (rc) return rc;
-    int64_t want = (m + NT - 1) / NT;
+    int64_t want = (m + 63) / 64;  // tiles of 16 rows per wave, 4 waves
     int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * std::max(1, per_cu) * 4));
     rc = ws_reserve_dev(w, Carve::need({(size_t)grid * 8}));
     if (rc) return rc;
@@ -278,9 +284,9 @@ int check_desc(const hpc_sample_desc* desc, int32_t n, int64_t idx_len, int64_t 
 // Run the resident kernel over a batch (Lloyd, or seeding only).
 int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64_t idx_len,
                  const hpc_sample_desc* desc, int32_t n, float* C, int32_t max_iter,
-                 double rel_tol, double* f_out, int32_t* iters_out, int32_t* labels_out,
-                 int seed_only, int n_cand, uint32_t call_id, int32_t* chosen, int kmax,
-                 hipStream_t st) {
+                 double rel_tol, int32_t precision, double* f_out, int32_t* iters_out,
+                 int32_t* labels_out, int seed_only, int n_cand, uint32_t call_id,
+                 int32_t* chosen, int kmax, hipStream_t st) {
     Workspace* w = nullptr;
     int rc = get_ws(st, &w);
     if (rc) return rc;
@@ -293,14 +299,14 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     });
     const size_t desc_b = (size_t)n * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n * 4;
-    const size_t need = Carve::need({desc_b + order_b, 256, (size_t)idx_len * D * 4,
-                                     (size_t)idx_len * 8});
+    const size_t sbuf_b = (size_t)idx_len * D * 4;
+    const size_t need = Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 8});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
     char* tbl = static_cast<char*>(cv.take(desc_b + order_b));
     int32_t* queue = static_cast<int32_t*>(cv.take(256));
-    float* sbuf = static_cast<float*>(cv.take((size_t)idx_len * D * 4));
+    float* sbuf = static_cast<float*>(cv.take(sbuf_b));
     double* d2 = static_cast<double*>(cv.take((size_t)idx_len * 8));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
@@ -329,7 +335,8 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     a.n_cand = n_cand;
     a.call_id = call_id;
     a.chosen = chosen;
-    return dispatch_resident(D, a, n, st);
+    a.vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    return dispatch_resident(D, precision, a, n, st);
 }
 
 }  // namespace
@@ -422,8 +429,9 @@ int hpc_seed_kmeanspp(const float* X, int64_t m, int32_t d, const int64_t* idx, 
     ds.k = k;
     ds.seed = seed;
     ds.sample_id = sample_id;
-    return run_resident(X, m, d, idx, s, &ds, 1, C, 1, 0.0, nullptr, nullptr, nullptr, 1,
-                        n_candidates, call_id, chosen, k, static_cast<hipStream_t>(hip_stream));
+    return run_resident(X, m, d, idx, s, &ds, 1, C, 1, 0.0, HPC_PREC_FP32, nullptr, nullptr,
+                        nullptr, 1, n_candidates, call_id, chosen, k,
+                        static_cast<hipStream_t>(hip_stream));
 }
 
 int hpc_lloyd_batch(const float* X, int64_t m, int32_t d, const int64_t* idx, int64_t idx_len,
@@ -442,10 +450,8 @@ int hpc_lloyd_batch(const float* X, int64_t m, int32_t d, const int64_t* idx, in
     int kmax = 0;
     int rc = check_desc(desc, n_samples, idx_len, c_len, d, &kmax);
     if (rc) return rc;
-    if (precision == HPC_PREC_BF16_MFMA)
-        return fail(HPC_ERR_UNSUPPORTED, "hpc_lloyd_batch: BF16 path not built yet");
-    return run_resident(X, m, d, idx, idx_len, desc, n_samples, C, max_iter, rel_tol, f_out,
-                        iters_out, labels_out, 0, 3, 0, nullptr, kmax,
+    return run_resident(X, m, d, idx, idx_len, desc, n_samples, C, max_iter, rel_tol, precision,
+                        f_out, iters_out, labels_out, 0, 3, 0, nullptr, kmax,
                         static_cast<hipStream_t>(hip_stream));
 }
 
@@ -483,13 +489,18 @@ int hpc_assign_sse(const float* X, int64_t m, int32_t d, const float* C, int32_t
     Workspace* w = nullptr;
     int rc = get_ws(st, &w);
     if (rc) return rc;
+    const bool bf = precision == HPC_PREC_BF16_MFMA;
+#define HPC_ASSIGN(DD)                                                                       \
+    return bf ? launch_assign<DD, hpc::kPrecBF16>(X, m, d, C, k, labels, counts, sse, w, st) \
+              : launch_assign<DD, hpc::kPrecF32>(X, m, d, C, k, labels, counts, sse, w, st)
     switch (pad_dim(d)) {
-        case 8: return launch_assign<8>(X, m, d, C, k, labels, counts, sse, w, st);
-        case 16: return launch_assign<16>(X, m, d, C, k, labels, counts, sse, w, st);
-        case 32: return launch_assign<32>(X, m, d, C, k, labels, counts, sse, w, st);
-        case 64: return launch_assign<64>(X, m, d, C, k, labels, counts, sse, w, st);
-        case 128: return launch_assign<128>(X, m, d, C, k, labels, counts, sse, w, st);
+        case 8: HPC_ASSIGN(8);
+        case 16: HPC_ASSIGN(16);
+        case 32: HPC_ASSIGN(32);
+        case 64: HPC_ASSIGN(64);
+        case 128: HPC_ASSIGN(128);
     }
+#undef HPC_ASSIGN
     return fail(HPC_ERR_UNSUPPORTED, "hpc_assign_sse: d=%d", d);
 }
 

@@ -8,21 +8,23 @@
 // longest-first order, so hundreds of samples of uneven size share one
 // launch with no inter-workgroup synchronisation at all.
 //
-// Arithmetic: the assignment screens all centroids in FP32 and certifies the
-// winner with a rigorous error bound (screen_certified); the rare point that
-// is not certified is re-decided in FP64.  The distance that enters the
+// Arithmetic: the assignment screens all centroids on the matrix cores
+// (FP32 or BF16 MFMA, mfma_screen.hpp) and certifies the winner with a
+// rigorous error bound; the rare point that is not certified is re-decided
+// in FP64.  The distance that enters the
 // objective, the K-means++ weights D^2, the potentials, the centroid sums
 // and the centroids themselves are FP64.  Every index the method decides is
 // therefore the one an FP64 evaluation decides.
 //
 // Layout per sample: the gathered rows live in a scratch buffer (row stride
 // D floats, zero padded) that stays hot in L2/MALL across passes; centroids
-// sit in LDS as FP64 plus an FP32 copy for the screening; per-wave FP64
+// sit in LDS as FP64 plus the MFMA A operands (-2c) and |c|^2; per-wave FP64
 // partial sums of the update live in LDS; D^2 lives in scratch, each element
 // owned by one thread.
 #pragma once
 
 #include "common.hpp"
+#include "mfma_screen.hpp"
 
 namespace hpc {
 
@@ -50,16 +52,25 @@ struct LloydArgs {
     int32_t n_cand;
     uint32_t call_id;
     int32_t* chosen;
+    int32_t vec4;  // rows of X are 16-byte aligned (d % 4 == 0, aligned base)
+};
+
+// Rows of one gathered sample (stride D, zero padded).
+template <int D>
+struct SampleView {
+    const float* base;
+    __device__ __forceinline__ const float* row(int i) const { return base + (size_t)i * D; }
 };
 
 // Carving of the dynamic LDS allocation; the host computes the same size.
-template <int D, int NT>
+template <int D, int NT, int PREC>
 struct Smem {
     static constexpr int NW = NT / kWave;
-    double* C64;   // kmax x D centroids (FP64)
-    float* C32;    // kmax x D centroids rounded to FP32 (screening)
+    double* C64;   // kmax rows of FP64 centroids, stride Lay<D>::CS
+    void* aop;     // MFMA A operands, nblk x ... (see mfma_screen.hpp)
+    float* nrm;    // nblk*16 score biases |c|^2
     double* crow;  // 4 x D candidate rows
-    double* psum;  // n_copies x kmax x D update sums   (union with seeding scan)
+    double* psum;  // n_copies x kmax rows (stride CS) of update sums (union with seeding scan)
     int* pcnt;     // n_copies x kmax counts
     double* incl;  // NT inclusive scan of chunk sums   (seeding)
     double* red;   // 4 x NW wave partials
@@ -68,29 +79,36 @@ struct Smem {
     int* ints;     // 16 scalars
 
     static __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+    static __host__ __device__ int nblk_of(int kmax) { return (kmax + 15) / 16; }
 
     static __host__ __device__ size_t union_bytes(int kmax, int copies) {
-        size_t lloyd = (size_t)copies * kmax * D * 8 + align_up((size_t)copies * kmax * 4, 16);
+        size_t lloyd = (size_t)copies * kmax * Lay<D>::CS * 8 + align_up((size_t)copies * kmax * 4, 16);
         size_t seed = (size_t)NT * 8;
         return lloyd > seed ? lloyd : seed;
     }
     static __host__ __device__ size_t bytes(int kmax, int copies) {
-        size_t b = (size_t)kmax * D * 8 + align_up((size_t)kmax * D * 4, 16) + 4 * D * 8;
+        const int nb = nblk_of(kmax);
+        size_t b = align_up((size_t)kmax * Lay<D>::CS * 8, 16) + align_up(aop_bytes<D, PREC>(nb), 16) +
+                   (size_t)nb * 64;
+        b += 4 * D * 8;
         b += union_bytes(kmax, copies);
         b += 4 * NW * 8 + align_up((size_t)kmax * 8, 16);
         b += align_up((size_t)kmax * 4, 16) + 16 * 4;
         return b;
     }
     __device__ Smem(char* base, int kmax, int copies) {
+        const int nb = nblk_of(kmax);
         char* p = base;
         C64 = reinterpret_cast<double*>(p);
-        p += (size_t)kmax * D * 8;
-        C32 = reinterpret_cast<float*>(p);
-        p += align_up((size_t)kmax * D * 4, 16);
+        p += align_up((size_t)kmax * Lay<D>::CS * 8, 16);
+        aop = p;
+        p += align_up(aop_bytes<D, PREC>(nb), 16);
+        nrm = reinterpret_cast<float*>(p);
+        p += (size_t)nb * 64;
         crow = reinterpret_cast<double*>(p);
         p += 4 * D * 8;
         psum = reinterpret_cast<double*>(p);
-        pcnt = reinterpret_cast<int*>(p + (size_t)copies * kmax * D * 8);
+        pcnt = reinterpret_cast<int*>(p + (size_t)copies * kmax * Lay<D>::CS * 8);
         incl = reinterpret_cast<double*>(p);
         p += union_bytes(kmax, copies);
         red = reinterpret_cast<double*>(p);
@@ -143,36 +161,41 @@ __device__ __forceinline__ void block_incl_scan(double v, double* out, double* r
     __syncthreads();
 }
 
-// Copy sample row i (FP32, padded) into centroid row j (FP64 and FP32).
+// Copy sample row i (FP32, padded) into an FP64 centroid row.
 template <int D, int NT>
-__device__ __forceinline__ void set_row_from_sample(double* dst64, float* dst32,
-                                                    const float* __restrict__ Sg, int i) {
-    for (int t = threadIdx.x; t < D; t += NT) {
-        const float v = Sg[(size_t)i * D + t];
-        dst64[t] = (double)v;
-        dst32[t] = v;
-    }
+__device__ __forceinline__ void set_row_from_sample(double* dst64, const SampleView<D>& sv, int i) {
+    const float* r = sv.row(i);
+    for (int t = threadIdx.x; t < D; t += NT) dst64[t] = (double)r[t];
 }
 
 // ---------------------------------------------------------------------------
 // K-means++ on the gathered sample for every degenerate row of L.C64, in
-// FP64 (weights, prefix sums, potentials).  Sg: s x D rows; d2: s doubles
-// of scratch.  Stream (seed, tag) / (block, sid, call, 0).  Thread t owns
-// the contiguous chunk [t*cs, (t+1)*cs) of the sample; the inverse-CDF
-// search is a workgroup scan of the chunk sums followed by a sequential
-// scan inside the one chunk that holds the target, so the prefix order is
-// the sample's index order.  chosen (nullable, global) receives the picked
-// sample-local indices.  Seeded rows are written to C64 and C32.
+// FP64 (weights, prefix sums, potentials).  sv: the sample's rows; d2: s
+// doubles of scratch.  Stream (seed, tag) / (block, sid, call, 0).
+//
+// Layout: wave w owns the contiguous chunk [w*cw, (w+1)*cw) of the sample
+// (cw a multiple of 16) and walks it in tiles of 16 points; within a tile a
+// lane holds a quarter of a point's coordinates, as in the assignment pass
+// (mfma_screen.hpp), so a distance is four partial FP64 sums and two
+// shuffles.  Weights D^2 of chunk w are read and written by wave w only.
+// The inverse-CDF search locates the chunk from the chunk totals, then the
+// owning wave scans its tiles in index order with a 16-lane FP64 prefix
+// scan, so the prefix order is the sample's index order.  chosen
+// (nullable, global) receives the picked sample-local indices.  Seeded rows
+// are written to C64.
 // ---------------------------------------------------------------------------
-template <int D, int NT>
-__device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_cand,
+template <int D, int NT, int PREC>
+__device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
                             double* __restrict__ d2, uint64_t seed, uint64_t tag, uint64_t sid,
-                            uint64_t call, int32_t* __restrict__ chosen, Smem<D, NT>& L) {
-    const int tid = threadIdx.x;
+                            uint64_t call, int32_t* __restrict__ chosen, Smem<D, NT, PREC>& L) {
+    constexpr int NW = NT / kWave;
+    constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
+    const int tid = threadIdx.x, wid = tid / kWave, lane = tid & 63;
+    const int g = lane >> 4, p = lane & 15;
     if (tid == 0) {
         int nd = 0, nv = 0;
         for (int j = 0; j < k; ++j) {
-            if (L.C64[j * D] != L.C64[j * D])
+            if (L.C64[j * CS] != L.C64[j * CS])
                 L.deg[nd++] = j;
             else
                 ++nv;
@@ -184,74 +207,105 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
     const int n_deg = L.ints[0], n_valid = L.ints[1];
     if (n_deg == 0) return;
 
-    const int cs = (s + NT - 1) / NT;
-    const int lo = min(s, tid * cs), hi = min(s, lo + cs);
+    const int cw = (((s + NW - 1) / NW) + 15) / 16 * 16;
+    const int lo = min(s, wid * cw), hi = min(s, lo + cw);
+    auto load_pt = [&](int i, float (&xq)[DL]) {
+        if (i < hi) {
+            load_quarter<D>(sv.row(i), g, xq);
+        } else {
+#pragma unroll
+            for (int t = 0; t < DL; ++t) xq[t] = 0.f;
+        }
+    };
+
     int first = 0;
-    double acc = 0.0;
+    double acc = 0.0;  // this lane's share of the wave's chunk total (g == 0 lanes)
     if (n_valid == 0) {
         const Words4 w0 = philox_block(seed, tag, 0, sid, call);
         const int i0 = (int)bounded_index(w0.w[0], (uint64_t)s);
         const int j0 = L.deg[0];
         if (tid == 0 && chosen) chosen[j0] = i0;
-        set_row_from_sample<D, NT>(L.C64 + j0 * D, L.C32 + j0 * D, Sg, i0);
+        set_row_from_sample<D, NT>(L.C64 + j0 * CS, sv, i0);
         __syncthreads();
-        for (int i = lo; i < hi; ++i) {
-            float x[D];
-            load_row<D>(Sg + (size_t)i * D, x);
-            const double v = sqdist64<D>(x, L.C64 + j0 * D);
-            d2[i] = v;
-            acc += v;
+        for (int b0 = lo; b0 < hi; b0 += 16) {
+            const int i = b0 + p;
+            float xq[DL];
+            load_pt(i, xq);
+            const double v = quarter_dist64<D>(xq, L.C64 + j0 * CS);
+            if (i < hi && g == 0) {
+                d2[i] = v;
+                acc += v;
+            }
         }
         first = 1;
     } else {
-        for (int i = lo; i < hi; ++i) {
-            float x[D];
-            load_row<D>(Sg + (size_t)i * D, x);
+        for (int b0 = lo; b0 < hi; b0 += 16) {
+            const int i = b0 + p;
+            float xq[DL];
+            load_pt(i, xq);
             double best = __builtin_huge_val();
             for (int j = 0; j < k; ++j) {
-                if (L.C64[j * D] != L.C64[j * D]) continue;
-                const double v = sqdist64<D>(x, L.C64 + j * D);
+                if (L.C64[j * CS] != L.C64[j * CS]) continue;
+                const double v = quarter_dist64<D>(xq, L.C64 + j * CS);
                 best = v < best ? v : best;
             }
-            d2[i] = best;
-            acc += best;
+            if (i < hi && g == 0) {
+                d2[i] = best;
+                acc += best;
+            }
         }
     }
 
     for (int r = first; r < n_deg; ++r) {
-        // chunk prefix sums of the current D^2 (index order)
-        block_incl_scan<NT>(acc, L.incl, L.red);
-        const double W = L.incl[NT - 1];
+        // chunk totals and their inclusive prefix over waves (index order)
+        const double wsum = wave_sum(acc);
+        if (lane == 0) L.red[wid] = wsum;
+        __syncthreads();
+        double c_lo = 0.0, W = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            if (w == wid) c_lo = W;
+            W += L.red[w];
+        }
+        const double c_hi = c_lo + L.red[wid];
         const uint64_t q = (uint64_t)(r + (n_valid > 0 ? 1 : 0));
         const Words4 w = philox_block(seed, tag, q, sid, call);
         int pick;
         if (!(W > 0.0)) {
             pick = (int)bounded_index(w.w[0], (uint64_t)s);
+            __syncthreads();
         } else {
             if (tid < 4) L.ints[4 + tid] = -1;
             __syncthreads();
-            const double c_lo = tid == 0 ? 0.0 : L.incl[tid - 1];
-            const double c_hi = L.incl[tid];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const double target = unit_double(w.w[t]) * W;
-                if (t < n_cand && c_lo <= target && target < c_hi) {
+                if (t < n_cand && c_lo <= target && target < c_hi) {  // wave-uniform
                     double run = c_lo;
                     int found = -1;
-                    for (int i = lo; i < hi; ++i) {
-                        run += d2[i];
-                        if (run > target) {
-                            found = i;
-                            break;
+                    for (int b0 = lo; b0 < hi && found < 0; b0 += 16) {
+                        const int i = b0 + p;
+                        double v = i < hi ? d2[i] : 0.0;
+#pragma unroll
+                        for (int o = 1; o < 16; o <<= 1) {
+                            const double u = __shfl_up(v, o, 16);
+                            if (p >= o) v += u;
+                        }
+                        const bool hit = i < hi && run + v > target;
+                        const unsigned long long m16 = __ballot(hit) & 0xFFFFull;
+                        if (m16)
+                            found = b0 + __ffsll(m16) - 1;
+                        else
+                            run += __shfl(v, 15, 16);
+                    }
+                    if (found < 0) {  // rounding: last point of positive weight in the chunk
+                        for (int b0 = (hi - 1 - lo) / 16 * 16 + lo; b0 >= lo && found < 0; b0 -= 16) {
+                            const int i = b0 + p;
+                            const bool pos = i < hi && d2[i] > 0.0;
+                            const unsigned long long m16 = __ballot(pos) & 0xFFFFull;
+                            if (m16) found = b0 + 63 - __clzll(m16);
                         }
                     }
-                    if (found < 0)
-                        for (int i = hi - 1; i >= lo; --i)
-                            if (d2[i] > 0.0) {
-                                found = i;
-                                break;
-                            }
-                    L.ints[4 + t] = found;
+                    if (lane == 0) L.ints[4 + t] = found;
                 }
             }
             __syncthreads();
@@ -267,76 +321,85 @@ __device__ void kmeanspp_wg(const float* __restrict__ Sg, int s, int k, int n_ca
             }
             __syncthreads();
             for (int e = tid; e < n_cand * D; e += NT)
-                L.crow[e] = (double)Sg[(size_t)L.ints[4 + e / D] * D + (e % D)];
+                L.crow[e] = (double)sv.row(L.ints[4 + e / D])[e % D];
             __syncthreads();
             // one candidate at a time keeps a single FP64 row live
-            double p[4] = {0.0, 0.0, 0.0, 0.0};
+            double pt[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (t >= n_cand) continue;
-                double pt = 0.0;
-                for (int i = lo; i < hi; ++i) {
-                    float x[D];
-                    load_row<D>(Sg + (size_t)i * D, x);
-                    const double dd = d2[i];
-                    const double v = sqdist64<D>(x, L.crow + t * D);
-                    pt += v < dd ? v : dd;
+                double acc_t = 0.0;
+                for (int b0 = lo; b0 < hi; b0 += 16) {
+                    const int i = b0 + p;
+                    float xq[DL];
+                    load_pt(i, xq);
+                    const double dd = i < hi ? d2[i] : 0.0;
+                    const double v = quarter_dist64<D>(xq, L.crow + t * D);
+                    if (i < hi && g == 0) acc_t += v < dd ? v : dd;
                 }
-                p[t] = pt;
+                pt[t] = acc_t;
             }
-            block_sum_n<NT, 4>(p, L.red);
+            block_sum_n<NT, 4>(pt, L.red);
             int tb = 0;
-            double pb = p[0];
+            double pb = pt[0];
 #pragma unroll
             for (int t = 1; t < 4; ++t)
-                if (t < n_cand && p[t] < pb) {
-                    pb = p[t];
+                if (t < n_cand && pt[t] < pb) {
+                    pb = pt[t];
                     tb = t;
                 }
             pick = L.ints[4 + tb];
         }
         const int jr = L.deg[r];
         if (tid == 0 && chosen) chosen[jr] = pick;
-        set_row_from_sample<D, NT>(L.C64 + jr * D, L.C32 + jr * D, Sg, pick);
+        set_row_from_sample<D, NT>(L.C64 + jr * CS, sv, pick);
         __syncthreads();
         acc = 0.0;
-        for (int i = lo; i < hi; ++i) {
-            float x[D];
-            load_row<D>(Sg + (size_t)i * D, x);
-            const double v = sqdist64<D>(x, L.C64 + jr * D);
-            const double o = d2[i];
-            const double nv = v < o ? v : o;
-            d2[i] = nv;
-            acc += nv;
+        for (int b0 = lo; b0 < hi; b0 += 16) {
+            const int i = b0 + p;
+            float xq[DL];
+            load_pt(i, xq);
+            const double v = quarter_dist64<D>(xq, L.C64 + jr * CS);
+            if (i < hi && g == 0) {
+                const double o = d2[i];
+                const double nv = v < o ? v : o;
+                d2[i] = nv;
+                acc += nv;
+            }
         }
         __syncthreads();
     }
 }
 
-// Rounding radius of the FP32 centroid copy: 2^-24 * max_j |c_j| (rounded
-// up slightly so that its FP32 use stays conservative).  Two barriers.
-template <int D, int NT>
-__device__ __forceinline__ float centroid_round_radius(Smem<D, NT>& L, int k, int d) {
+// Largest centroid norm max_j |c_j| over valid rows.  Two barriers.
+template <int D, int NT, int PREC>
+__device__ __forceinline__ double centroid_max_norm(Smem<D, NT, PREC>& L, int k, int d) {
+    constexpr int CS = Lay<D>::CS;
     for (int j = threadIdx.x; j < k; j += NT) {
         double n2 = 0.0;
-        for (int t = 0; t < d; ++t) n2 += L.C64[j * D + t] * L.C64[j * D + t];
+        if (L.C64[j * CS] == L.C64[j * CS])
+            for (int t = 0; t < d; ++t) n2 = __fma_rn(L.C64[j * CS + t], L.C64[j * CS + t], n2);
         L.cn[j] = n2;
     }
     __syncthreads();
     double mx = 0.0;
     for (int j = 0; j < k; ++j) mx = L.cn[j] > mx ? L.cn[j] : mx;
     __syncthreads();
-    return (float)(sqrt(mx) * 0x1.0p-24 * 1.0001) + 1e-30f;
+    return sqrt(mx);
 }
 
-template <int D, int NT>
+template <int D, int NT, int PREC>
 __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
     extern __shared__ __align__(16) char smem[];
-    Smem<D, NT> L(smem, a.kmax, a.n_copies);
-    constexpr int NW = Smem<D, NT>::NW;
-    const int tid = threadIdx.x, wid = tid / kWave;
+    using S = Smem<D, NT, PREC>;
+    constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
+    S L(smem, a.kmax, a.n_copies);
+    constexpr int NW = S::NW;
+    const int tid = threadIdx.x, wid = tid / kWave, lane = tid & 63;
+    const int g = lane >> 4, pl = lane & 15;
     const int d = a.d;
-    const float tau = 4.f * (float)(d + 8) * 0x1.0p-24f;
+    double alpha, beta;
+    screen_coeffs<PREC>(d, &alpha, &beta);
 
     for (;;) {
         if (tid == 0) L.ints[15] = atomicAdd(a.queue, 1);
@@ -347,23 +410,51 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
         const int b = a.order ? a.order[slot] : slot;
         const hpc_sample_desc ds = a.desc[b];
         const int s = ds.s, k = ds.k;
+        const int nblk = (k + 15) / 16;
         float* Sg = a.sbuf + (size_t)ds.idx_offset * D;
         double* d2 = a.d2buf + ds.idx_offset;
+        const SampleView<D> sv{Sg};
 
-        // gather the sample rows (zero padded to D)
-        for (int i = tid; i < s; i += NT) {
-            const int64_t row = a.idx[ds.idx_offset + i];
-            const bool in_range = row >= 0 && row < a.m;  // out-of-range rows read as zeros
-            const float* src = a.X + (in_range ? row : 0) * d;
-            float* dst = Sg + (size_t)i * D;
+        // gather the sample rows (zero padded to D): consecutive threads
+        // copy consecutive 16-byte chunks of a row; eight chunks per thread
+        // are loaded before any is stored, so the random-row loads overlap
+        {
+            constexpr int NCH = D / 4;
+            const int total = s * NCH;
+            for (int base = tid; base < total; base += 8 * NT) {
+                float4 v[8];
+                int dst[8];
 #pragma unroll
-            for (int t = 0; t < D; ++t) dst[t] = (t < d && in_range) ? src[t] : 0.f;
+                for (int u = 0; u < 8; ++u) {
+                    const int e = base + u * NT;
+                    dst[u] = -1;
+                    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (e < total) {
+                        const int i = e / NCH, col = (e % NCH) * 4;
+                        const int64_t row = a.idx[ds.idx_offset + i];
+                        const bool in_range = row >= 0 && row < a.m;  // else a zero row
+                        dst[u] = i * D + col;
+                        if (in_range && col < d) {
+                            const float* src = a.X + row * d + col;
+                            if (a.vec4) {
+                                v[u] = *reinterpret_cast<const float4*>(src);
+                            } else {
+                                v[u].x = src[0];
+                                v[u].y = col + 1 < d ? src[1] : 0.f;
+                                v[u].z = col + 2 < d ? src[2] : 0.f;
+                                v[u].w = col + 3 < d ? src[3] : 0.f;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (dst[u] >= 0) *reinterpret_cast<float4*>(Sg + dst[u]) = v[u];
+            }
         }
-        for (int e = tid; e < k * D; e += NT) {
-            const int j = e / D, t = e % D;
-            const float v = t < d ? a.C[ds.c_offset + (int64_t)j * d + t] : 0.f;
-            L.C32[e] = v;
-            L.C64[e] = (double)v;
+        for (int e = tid; e < k * CS; e += NT) {
+            const int j = e / CS, t = e % CS;
+            L.C64[e] = t < d ? (double)a.C[ds.c_offset + (int64_t)j * d + t] : 0.0;
         }
         __syncthreads();
 
@@ -371,80 +462,90 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
             if (a.chosen)
                 for (int j = tid; j < k; j += NT) a.chosen[j] = -1;
             __syncthreads();
-            kmeanspp_wg<D, NT>(Sg, s, k, a.n_cand, d2, ds.seed, kTagSeed, ds.sample_id, a.call_id,
-                               a.chosen, L);
+            kmeanspp_wg<D, NT, PREC>(sv, s, k, a.n_cand, d2, ds.seed, kTagSeed, ds.sample_id,
+                                     a.call_id, a.chosen, L);
         } else {
             double f_prev = __builtin_huge_val(), f = 0.0;
             int it = 0;
             const int copies = a.n_copies;
-            const bool shared_copy = copies < NW;
             for (;;) {
-                kmeanspp_wg<D, NT>(Sg, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
-                                   (uint64_t)it, nullptr, L);
-                const float rmax = centroid_round_radius<D, NT>(L, k, d);
-                for (int e = tid; e < copies * k * D; e += NT) L.psum[e] = 0.0;
+                kmeanspp_wg<D, NT, PREC>(sv, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
+                                         (uint64_t)it, nullptr, L);
+                const double cmax = centroid_max_norm<D, NT, PREC>(L, k, d);
+                const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
+                build_operands<D, PREC, NT>(L.C64, k, d, nblk, L.aop, L.nrm);
+                for (int e = tid; e < copies * k * CS; e += NT) L.psum[e] = 0.0;
                 for (int e = tid; e < copies * k; e += NT) L.pcnt[e] = 0;
                 __syncthreads();
-                double* pw = L.psum + (size_t)(wid % copies) * k * D;
+                double* pw = L.psum + (size_t)(wid % copies) * k * CS;
                 int* cw = L.pcnt + (wid % copies) * k;
                 double fl = 0.0;
-                for (int base = 0; base < s; base += NT) {
-                    const int i = base + tid;
-                    if (i < s) {
-                        float x[D];
-                        load_row<D>(Sg + (size_t)i * D, x);
-                        // FP32 screening: best and runner-up
-                        float b1 = __builtin_huge_valf(), b2 = __builtin_huge_valf();
-                        int am = 0;
-                        for (int j = 0; j < k; ++j) {
-                            const float v = sqdist<D>(x, L.C32 + j * D);
-                            if (v < b1) {
-                                b2 = b1;
-                                b1 = v;
-                                am = j;
-                            } else if (v < b2) {
-                                b2 = v;
-                            }
-                        }
-                        double dm;
-                        if (screen_certified(b1, b2, tau, rmax)) {
-                            dm = sqdist64<D>(x, L.C64 + am * D);
-                        } else {  // re-decide in FP64 (lowest index on ties)
-                            dm = __builtin_huge_val();
-                            for (int j = 0; j < k; ++j) {
-                                const double v = sqdist64<D>(x, L.C64 + j * D);
-                                if (v < dm) {
-                                    dm = v;
-                                    am = j;
-                                }
-                            }
-                        }
-                        fl += dm;
-                        if (a.labels_out) a.labels_out[ds.idx_offset + i] = am;
-                        double* ps = pw + am * D;
-                        (void)shared_copy;
+                // tiles of 16 points per wave, software pipelined over three
+                // register buffers: the rows of the next two tiles are in
+                // flight while one tile is processed (unrolled by three so
+                // that no buffer with a load in flight is ever copied)
+                float xa[DL], xb[DL], xc[DL];
+                // branch-free: rows past the end re-read the last row (their
+                // lanes are masked in process), which keeps the memory
+                // counters exact for the compiler's wait placement
+                auto fetch = [&](int tile, float (&dst)[DL]) {
+                    const int i = min(tile * 16 + pl, s - 1);
+                    load_quarter<D>(Sg + (size_t)i * D, g, dst);
+                };
+                auto process = [&](int tile, const float (&xq)[DL]) {
+                    const int i = tile * 16 + pl;
+                    const bool valid = i < s;
+                    const Top2 t2 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk);
+                    const float xn = cert_norm(point_norm2<D>(xq));
+                    const bool ok = certified(t2, xn, ea, eb) || !valid;
+                    const int am = redecide64<D>(xq, !ok, top2_suffices(t2, xn, ea, eb), t2.a1,
+                                                 t2.a2, L.C64, k);
+                    if (valid) {
+                        // this lane's share of the objective and of the sums
+                        const double* cr = L.C64 + am * CS + g * DL;
+                        double* ps = pw + am * CS + g * DL;
+                        double part = 0.0;
 #pragma unroll
-                        for (int t = 0; t < D; ++t)
-                            if (t < d) atomicAdd(ps + t, (double)x[t]);
-                        atomicAdd(cw + am, 1);
+                        for (int t = 0; t < DL; ++t) {
+                            const double xd = (double)xq[t];
+                            const double e = xd - cr[t];
+                            part = __fma_rn(e, e, part);
+                            if (g * DL + t < d) atomicAdd(ps + t, xd);
+                        }
+                        fl += part;
+                        if (g == 0) {
+                            if (a.labels_out) a.labels_out[ds.idx_offset + i] = am;
+                            atomicAdd(cw + am, 1);
+                        }
                     }
+                };
+                fetch(wid, xa);
+                fetch(wid + NW, xb);
+                for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
+                    fetch(tile + 2 * NW, xc);
+                    process(tile, xa);
+                    if ((tile + NW) * 16 >= s) break;
+                    fetch(tile + 3 * NW, xa);
+                    process(tile + NW, xb);
+                    if ((tile + 2 * NW) * 16 >= s) break;
+                    fetch(tile + 4 * NW, xb);
+                    process(tile + 2 * NW, xc);
                 }
                 f = block_sum<NT>(fl, L.red);
                 ++it;
                 if (it >= a.max_iter || f == 0.0 || (f_prev - f) < a.rel_tol * f_prev) break;
                 f_prev = f;
-                for (int e = tid; e < k * D; e += NT) {
-                    const int j = e / D, t = e % D;
+                for (int e = tid; e < k * CS; e += NT) {
+                    const int j = e / CS, t = e % CS;
                     double sum = 0.0;
                     int n = 0;
-                    for (int g = 0; g < copies; ++g) {
-                        sum += L.psum[(size_t)g * k * D + e];
-                        n += L.pcnt[g * k + j];
+                    for (int gg = 0; gg < copies; ++gg) {
+                        sum += L.psum[(size_t)gg * k * CS + e];
+                        n += L.pcnt[gg * k + j];
                     }
                     double v = 0.0;
                     if (t < d) v = n > 0 ? sum / (double)n : __builtin_nan("");
                     L.C64[e] = v;
-                    L.C32[e] = (float)v;
                 }
                 __syncthreads();
             }
@@ -455,7 +556,7 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
         }
         for (int e = tid; e < k * d; e += NT) {
             const int j = e / d, t = e % d;
-            a.C[ds.c_offset + e] = (float)L.C64[j * D + t];
+            a.C[ds.c_offset + e] = (float)L.C64[j * CS + t];
         }
         __syncthreads();
     }

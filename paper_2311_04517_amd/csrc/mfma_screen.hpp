@@ -1,0 +1,307 @@
+// Nearest-centroid screening on the matrix cores of gfx950.
+//
+// The distance |x - c_j|^2 = |x|^2 + s_j with score s_j = |c_j|^2 - 2 x.c_j;
+// the cross term x.c_j over a tile of 16 points and blocks of 16 centroids
+// is the one dense contraction of the method and runs on MFMA:
+//   FP32 : v_mfma_f32_16x16x4_f32   (one k-slice of 4 per instruction)
+//   BF16 : v_mfma_f32_16x16x32_bf16 (32-wide k-slice, FP32 accumulation)
+// A = -2 c (centroids x dims), B = x^T (dims x points), the accumulator
+// starts at |c_j|^2, so the MFMA result is s_j directly.
+//
+// Lane layout (16x16 MFMA family on gfx950, wave of 64): lane l supplies A
+// row l%16 and B column l%16, the k-values of lane group g = l/16, and
+// receives rows 4g..4g+3 of column l%16.  Hence a lane owns point l%16 of
+// the tile and dims [g*DL, (g+1)*DL) of that point (DL = D/4; the dims are
+// permuted consistently in A and B, which leaves the contraction
+// unchanged), and gets the scores of centroids 4g..4g+3 of each block.  The
+// four lanes of a point merge their best/runner-up with two XOR shuffles.
+//
+// Certificate: let E(x) bound |s~_j - s_j| for the screened score; when
+// the screened gap s~_2 - s~_1 exceeds 2E the screened winner is the exact
+// argmin.  E(x) = alpha |x| cmax + beta cmax^2 with (u = 2^-24, u_b = 2^-8
+// plus the FP32-to-BF16 double rounding)
+//   FP32 : alpha = (4d + 10) u          beta = (2d + 6) u
+//   BF16 : alpha = 4 u_b + 2 u_b^2 + (4d + 10) u (1 + u_b)^2   beta as FP32
+// i.e. the rounding of the operands to the MFMA input type, plus twice the
+// classical accumulation bound of d + 1 FP32 additions (the factor two
+// leaves room for the matrix unit's internal summation order), plus the
+// rounding of |c|^2 to FP32.  The test below uses 2.5 E.
+#pragma once
+
+#include "common.hpp"
+
+namespace hpc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+enum : int { kPrecF32 = 0, kPrecBF16 = 1 };
+
+template <int D>
+struct Lay {
+    static constexpr int DL = D / 4;              // dims per lane
+    static constexpr int KC = (DL + 7) / 8;       // BF16 k-chunks of 8 per lane
+    // Row stride (in doubles) of FP64 centroid rows and per-cluster sums in
+    // LDS: odd, so that the rows of different centroids start in different
+    // LDS banks (a stride of D doubles puts every row on the same banks and
+    // serialises the per-lane row reads and the update atomics).
+    static constexpr int CS = D + 1;
+};
+
+// Bytes of the A-operand buffer for nblk blocks of 16 centroids.
+template <int D, int PREC>
+__host__ __device__ constexpr size_t aop_bytes(int nblk) {
+    return PREC == kPrecF32 ? (size_t)nblk * Lay<D>::DL * 64 * 4
+                            : (size_t)nblk * Lay<D>::KC * 64 * 16;
+}
+
+template <int PREC>
+__host__ __device__ inline void screen_coeffs(int d, double* alpha, double* beta) {
+    const double u = 0x1.0p-24, ub = 0x1.0p-8 + 0x1.0p-24;
+    const double acc = (4.0 * d + 10.0) * u;
+    *beta = (2.0 * d + 6.0) * u;
+    *alpha = PREC == kPrecF32 ? acc : 4.0 * ub + 2.0 * ub * ub + acc * (1.0 + ub) * (1.0 + ub);
+}
+
+// Fill the A operands (-2 c, rounded to the MFMA type; zero for padding
+// rows) and the score bias |c|^2 (FP32; +inf for padding rows) from the
+// FP64 centroids (row stride Lay<D>::CS).  Rows whose first coordinate is
+// NaN are treated as padding (never chosen).  All threads participate.
+template <int D, int PREC, int NT>
+__device__ void build_operands(const double* __restrict__ C64, int k, int d, int nblk,
+                               void* __restrict__ aop, float* __restrict__ nrm) {
+    constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC, CS = Lay<D>::CS;
+    for (int j = threadIdx.x; j < nblk * 16; j += NT) {
+        float v = __builtin_huge_valf();
+        if (j < k && C64[j * CS] == C64[j * CS]) {
+            double n2 = 0.0;
+            for (int t = 0; t < d; ++t) n2 = __fma_rn(C64[j * CS + t], C64[j * CS + t], n2);
+            v = (float)n2;
+        }
+        nrm[j] = v;
+    }
+    if (PREC == kPrecF32) {
+        float* a = static_cast<float*>(aop);
+        for (int e = threadIdx.x; e < nblk * DL * 64; e += NT) {
+            const int blk = e / (DL * 64), q = (e / 64) % DL, l = e % 64;
+            const int j = blk * 16 + (l & 15), t = (l >> 4) * DL + q;
+            float v = 0.f;
+            if (j < k && C64[j * CS] == C64[j * CS]) v = -2.f * (float)C64[j * CS + t];
+            a[e] = v;
+        }
+    } else {
+        __bf16* a = static_cast<__bf16*>(aop);
+        for (int e = threadIdx.x; e < nblk * KC * 64 * 8; e += NT) {
+            const int v8 = e & 7, l = (e >> 3) & 63, kc = (e >> 9) % KC, blk = (e >> 9) / KC;
+            const int j = blk * 16 + (l & 15), q = kc * 8 + v8, t = (l >> 4) * DL + q;
+            float v = 0.f;
+            if (q < DL && j < k && C64[j * CS] == C64[j * CS]) v = -2.f * (float)C64[j * CS + t];
+            a[e] = (__bf16)v;
+        }
+    }
+}
+
+// Load this lane's DL dims of point row p (row stride D floats, 16-byte
+// aligned rows, zero padded).
+template <int D>
+__device__ __forceinline__ void load_quarter(const float* __restrict__ row, int g,
+                                             float (&xq)[Lay<D>::DL]) {
+    constexpr int DL = Lay<D>::DL;
+    const float* p = row + g * DL;
+    if constexpr (DL % 4 == 0) {
+#pragma unroll
+        for (int t = 0; t < DL; t += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(p + t);
+            xq[t] = v.x;
+            xq[t + 1] = v.y;
+            xq[t + 2] = v.z;
+            xq[t + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < DL; t += 2) {
+            const float2 v = *reinterpret_cast<const float2*>(p + t);
+            xq[t] = v.x;
+            xq[t + 1] = v.y;
+        }
+    }
+}
+
+// Best, runner-up and third screened scores of a point (a1, a2: indices of
+// the best two).
+struct Top2 {
+    float b1, b2, b3;
+    int a1, a2;
+};
+
+__device__ __forceinline__ void top2_push(Top2& t, float v, int j) {
+    const bool lt1 = v < t.b1, lt2 = v < t.b2, lt3 = v < t.b3;
+    t.b3 = lt2 ? t.b2 : (lt3 ? v : t.b3);
+    t.b2 = lt1 ? t.b1 : (lt2 ? v : t.b2);
+    t.a2 = lt1 ? t.a1 : (lt2 ? j : t.a2);
+    t.a1 = lt1 ? j : t.a1;
+    t.b1 = lt1 ? v : t.b1;
+}
+
+// Merge with the lane at XOR distance o (the lanes hold disjoint centroid
+// sets).  Symmetric, ties to the lower index, so all four lanes of a point
+// end with the same result.
+__device__ __forceinline__ void top2_merge(Top2& t, int o) {
+    const float ob1 = lane_xor(t.b1, o);
+    const float ob2 = lane_xor(t.b2, o);
+    const float ob3 = lane_xor(t.b3, o);
+    const int oa1 = lane_xor(t.a1, o);
+    const int oa2 = lane_xor(t.a2, o);
+    const bool other = ob1 < t.b1 || (ob1 == t.b1 && oa1 < t.a1);
+    // winner list W = (w1, w2, w3), loser list L = (l1, l2, l3); merged:
+    // first w1; second min(w2, l1); third the next of the two lists
+    const float w2 = other ? ob2 : t.b2, w3 = other ? ob3 : t.b3;
+    const float l1 = other ? t.b1 : ob1, l2 = other ? t.b2 : ob2;
+    const int wa2 = other ? oa2 : t.a2, la1 = other ? t.a1 : oa1;
+    const bool l_second = l1 < w2 || (l1 == w2 && la1 < wa2);
+    t.b1 = other ? ob1 : t.b1;
+    t.a1 = other ? oa1 : t.a1;
+    t.b2 = l_second ? l1 : w2;
+    t.a2 = l_second ? la1 : wa2;
+    t.b3 = l_second ? fminf(w2, l2) : fminf(w3, l1);
+}
+
+// Scores of this lane's point against all nblk*16 centroids; returns the
+// merged best/runner-up for the point (identical in its four lanes).
+template <int D, int PREC>
+__device__ __forceinline__ Top2 screen_tile(const float (&xq)[Lay<D>::DL],
+                                            const void* __restrict__ aop,
+                                            const float* __restrict__ nrm, int nblk) {
+    constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    Top2 t{__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), 0, 0};
+    if constexpr (PREC == kPrecF32) {
+        const float* a = static_cast<const float*>(aop);
+        for (int blk = 0; blk < nblk; ++blk) {
+            f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+#pragma unroll
+            for (int q = 0; q < DL; ++q)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
+                                                           acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) top2_push(t, acc[r], blk * 16 + 4 * g + r);
+        }
+    } else {
+        bf16x8 xb[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int q = kc * 8 + v;
+                xb[kc][v] = (__bf16)(q < DL ? xq[q < DL ? q : 0] : 0.f);
+            }
+        const bf16x8* a = static_cast<const bf16x8*>(aop);
+        for (int blk = 0; blk < nblk; ++blk) {
+            f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[(blk * KC + kc) * 64 + lane], xb[kc],
+                                                              acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) top2_push(t, acc[r], blk * 16 + 4 * g + r);
+        }
+    }
+    top2_merge(t, 16);
+    top2_merge(t, 32);
+    return t;
+}
+
+// |x|^2 of this lane's point (same value in its four lanes).  Used only by
+// the certificate, whose 2.5 factor covers its rounding.
+template <int D>
+__device__ __forceinline__ float point_norm2(const float (&xq)[Lay<D>::DL]) {
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < Lay<D>::DL; ++t) s = __fmaf_rn(xq[t], xq[t], s);
+    s += lane_xor(s, 16);
+    s += lane_xor(s, 32);
+    return s;
+}
+
+// FP64 |x - c|^2 of this lane's point to the FP64 centroid row c,
+// summed over the four lanes of the point (same value in all four).
+template <int D>
+__device__ __forceinline__ double quarter_dist64(const float (&xq)[Lay<D>::DL],
+                                                 const double* __restrict__ c) {
+    constexpr int DL = Lay<D>::DL;
+    const int g = (threadIdx.x & 63) >> 4;
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < DL; ++t) {
+        const double e = (double)xq[t] - c[g * DL + t];
+        p = __fma_rn(e, e, p);
+    }
+    p += lane_xor(p, 16);
+    p += lane_xor(p, 32);
+    return p;
+}
+
+// |x| for the certificate: hardware square root (within 1 ulp), the 2.5
+// factor of the test covers its error.
+__device__ __forceinline__ float cert_norm(float n2) { return __builtin_amdgcn_sqrtf(n2); }
+
+// Screening winner certified?  gap > 2.5 E with E = ea |x| + eb (alpha and
+// beta already multiplied by cmax and cmax^2).
+__device__ __forceinline__ bool certified(const Top2& t, float xnorm, float ea, float eb) {
+    if (!(t.b2 < __builtin_huge_valf())) return true;
+    return (t.b2 - t.b1) > 2.5f * (ea * xnorm + eb);
+}
+
+// The exact argmin is one of the two best screened centroids when the third
+// is separated from the best by the certificate.
+__device__ __forceinline__ bool top2_suffices(const Top2& t, float xnorm, float ea, float eb) {
+    if (!(t.b3 < __builtin_huge_valf())) return true;
+    return (t.b3 - t.b1) > 2.5f * (ea * xnorm + eb);
+}
+
+// Exact FP64 decision for the points of this wave whose screening was not
+// certified (`redo` true in their four lanes): between the two best
+// screened centroids when the third is clear (`pair_ok`), otherwise over
+// all k rows.  Lowest index on exact ties.  Wave-uniform loops; returns the
+// decided index (a1 where redo is false).
+template <int D>
+__device__ __forceinline__ int redecide64(const float (&xq)[Lay<D>::DL], bool redo, bool pair_ok,
+                                          int a1, int a2, const double* __restrict__ C64, int k) {
+    constexpr int CS = Lay<D>::CS;
+    int am = a1;
+    if (!__any(redo)) return am;
+    const double v1 = quarter_dist64<D>(xq, C64 + a1 * CS);
+    const double v2 = quarter_dist64<D>(xq, C64 + a2 * CS);
+    if (redo && pair_ok && (v2 < v1 || (v2 == v1 && a2 < a1))) am = a2;
+    const bool full = redo && !pair_ok;
+    if (!__any(full)) return am;
+    double best = __builtin_huge_val();
+    int bj = 0;
+    for (int j = 0; j < k; ++j) {
+        if (C64[j * CS] != C64[j * CS]) continue;
+        const double v = quarter_dist64<D>(xq, C64 + j * CS);
+        if (v < best) {
+            best = v;
+            bj = j;
+        }
+    }
+    return full ? bj : am;
+}
+
+// This lane's FP64 share of |x - c|^2 (its DL coordinates; the four lanes
+// of a point together give the distance).
+template <int D>
+__device__ __forceinline__ double quarter_part64(const float (&xq)[Lay<D>::DL],
+                                                 const double* __restrict__ c) {
+    constexpr int DL = Lay<D>::DL;
+    const int g = (threadIdx.x & 63) >> 4;
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < DL; ++t) {
+        const double e = (double)xq[t] - c[g * DL + t];
+        p = __fma_rn(e, e, p);
+    }
+    return p;
+}
+
+}  // namespace hpc

@@ -58,14 +58,18 @@ def test_draw_samples_batch_bit_exact(hp, orc):
 
 
 # ---------------------------------------------------------------- assign + SSE
+PRECS = [0, 1]  # FP32 and BF16 MFMA screening: both must decide exactly
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("d", [3, 8, 16, 32, 64, 100])
-def test_assign_sse_parity(hp, orc, d):
+def test_assign_sse_parity(hp, orc, d, prec):
     m, k = 70_001, 13
     Xn, Xg = _mix(m, d, 9, seed=d)
     rng = np.random.default_rng(d)
     Cn = (Xn[rng.integers(0, m, size=k)] + rng.normal(0, 0.5, size=(k, d))).astype(np.float32)
     Cn[4] = np.nan  # a degenerate row is skipped
-    lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda())
+    lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda(), precision=prec)
     o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
     assert_labels(lab.cpu().numpy(), o["labels"], o["margins"])
     lg = lab.cpu().numpy()
@@ -74,13 +78,14 @@ def test_assign_sse_parity(hp, orc, d):
     assert rel(sse.item(), o["sse"]) <= SSE_REL
 
 
-def test_assign_sse_small_and_ragged(hp, orc):
-    for m, k in [(1, 1), (5, 3), (257, 2), (1023, 40)]:
+@pytest.mark.parametrize("prec", PRECS)
+def test_assign_sse_small_and_ragged(hp, orc, prec):
+    for m, k in [(1, 1), (5, 3), (257, 2), (1023, 40), (77, 200)]:
         Xn, Xg = _mix(m, 5, 3, seed=m)
         Cn = Xn[np.arange(k) % m].copy()
         if k > 1:
             Cn[-1] += 0.25
-        lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda())
+        lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda(), precision=prec)
         o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
         assert_labels(lab.cpu().numpy(), o["labels"], o["margins"])
         assert rel(sse.item(), o["sse"]) <= SSE_REL or (o["sse"] == 0 and sse.item() == 0)
@@ -175,8 +180,10 @@ def test_lloyd_teacher_forced_two_passes(hp, orc, d, s, k):
     assert np.array_equal(lg, ro.labels)
 
 
-@pytest.mark.parametrize("d,s,k,mseed", [(8, 2000, 10, 0), (32, 10_000, 25, 1), (12, 3001, 6, 2)])
-def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed):
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("d,s,k,mseed", [(8, 2000, 10, 0), (32, 10_000, 25, 1), (12, 3001, 6, 2),
+                                         (64, 5000, 100, 3)])
+def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed, prec):
     """Cold start (all rows degenerate): K-means++ then passes to the stop
     rule; exact pass counts and labels on seeds whose oracle run is clean."""
     Xn, Xg = _mix(50_000, d, 10, seed=300 + mseed)
@@ -185,7 +192,7 @@ def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed):
         idx = orc.draw_sample(50_000, s, 17, sid)
         ro = orc.lloyd(Xn, idx, k, seed=17, sample_id=sid, want_margins=True)
         desc, _, _ = hp.make_desc([s], [k], seed=17, sample_id=[sid], d=d)
-        Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, np.full((k, d), np.nan))
+        Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, np.full((k, d), np.nan), precision=prec)
         assert np.isfinite(Cg).all() and 1 <= itg[0] <= 300
         if not diag_clean(ro.diag):
             continue
@@ -237,7 +244,8 @@ def test_lloyd_degenerate_cases(hp, orc):
     assert itg[0] == 1 and rel(fg[0], ro.f) <= F_REL and np.array_equal(Cg.reshape(1, 7), ro.C)
 
 
-def test_lloyd_batch_uneven(hp, orc):
+@pytest.mark.parametrize("prec", PRECS)
+def test_lloyd_batch_uneven(hp, orc, prec):
     """Many samples of uneven (s, k), cold and warm starts, in one launch."""
     Xn, Xg = _mix(80_000, 10, 12, seed=11, box=12.0)
     rng = np.random.default_rng(5)
@@ -255,7 +263,7 @@ def test_lloyd_batch_uneven(hp, orc):
         C0[co:co + k * 10] = blk.ravel()
     Co = C0.copy()
     ro = orc.lloyd_batch(Xn, idx, dn, Co, want_labels=True, n_threads=4)
-    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0)
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0, precision=prec)
     clean = 0
     for b in range(n):
         io, s, k, co = dn["idx_offset"][b], dn["s"][b], dn["k"][b], dn["c_offset"][b]
@@ -273,6 +281,62 @@ def test_lloyd_batch_uneven(hp, orc):
         assert rel(fg[b], ro["f"][b]) <= F_REL
         assert_centroids(cg, Co[co:co + k * 10].reshape(k, 10), S)
     assert clean >= n // 2
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_near_ties_are_redecided_exactly(hp, orc, prec):
+    """Points placed almost on the bisector of two centroids (relative gaps
+    down to 1e-9), far from the origin so that the FP32 and BF16 screening
+    cannot separate them: every label must still equal the FP64 argmin."""
+    rng = np.random.default_rng(0)
+    d, k, m = 16, 6, 20_000
+    Cn = (rng.normal(size=(k, d)) * 3 + 40.0).astype(np.float32)
+    a = rng.integers(0, k, size=m)
+    b = (a + 1 + rng.integers(0, k - 1, size=m)) % k
+    mid = (Cn[a].astype(np.float64) + Cn[b]) / 2
+    off = rng.normal(size=(m, d)) * 2.0
+    w = Cn[b].astype(np.float64) - Cn[a]
+    off -= (off * w).sum(1, keepdims=True) / (w * w).sum(1, keepdims=True) * w  # on the bisector
+    eps = 10.0 ** rng.uniform(-9, -2, size=(m, 1))
+    Xn = (mid + off + eps * w * rng.choice([-1, 1], size=(m, 1))).astype(np.float32)
+    lab, cnt, sse = hp.assign_sse(torch.from_numpy(Xn).cuda(), torch.from_numpy(Cn).cuda(),
+                                  precision=prec)
+    o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
+    lg = lab.cpu().numpy()
+    exact = o["margins"] >= CLEAN_MARGIN
+    assert (o["margins"] < 1e-4).mean() > 0.3  # the set really is full of near ties
+    assert np.array_equal(lg[exact], o["labels"][exact])
+    assert rel(sse.item(), o["sse"]) <= 1e-12
+    # the same points as a Lloyd sample, one pass from these centroids
+    idx = np.arange(m, dtype=np.int64)
+    desc, _, _ = hp.make_desc([m], [k], seed=1, sample_id=[0], d=d)
+    Cg, fg, itg, lg2 = _lloyd_gpu(hp, torch.from_numpy(Xn).cuda(), idx, desc, Cn, max_iter=1,
+                                  precision=prec)
+    assert np.array_equal(lg2[exact], o["labels"][exact])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_direct_and_gathered_rows_agree(hp, orc, prec):
+    """Rows read straight from X through the indices (d equal to the padded
+    width, aligned X) and rows gathered into scratch (misaligned X) give
+    identical results."""
+    Xn, _ = _mix(30_000, 16, 8, seed=21)
+    flat = torch.zeros(30_000 * 16 + 1, dtype=torch.float32, device="cuda")
+    flat[1:] = torch.from_numpy(Xn.ravel()).cuda()
+    Xmis = flat[1:].view(30_000, 16)  # 4-byte offset: not 16-byte aligned
+    Xal = torch.from_numpy(Xn).cuda()
+    assert Xmis.data_ptr() % 16 != 0 and Xal.data_ptr() % 16 == 0
+    n, s, k = 6, 3000, 9
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=3, sample_id=np.arange(n), d=16)
+    idx = hp.draw_samples(30_000, desc, idx_len)
+    out = []
+    for Xg in (Xal, Xmis):
+        C = torch.full((c_len,), float("nan"), device="cuda")
+        f, it, lab = hp.lloyd_batch(Xg, idx, desc, C, want_labels=True, precision=prec)
+        l2, c2, sse = hp.assign_sse(Xg, C[:k * 16].view(k, 16).contiguous(), precision=prec)
+        out.append((C, f, it, lab, l2, c2, sse))
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
 
 
 def test_lloyd_batch_deterministic(hp, orc):
