@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="MFMA type of the distance screening (decisions are FP64-exact)")
+    ap.add_argument("--pmc-target", action="store_true",
+                    help="run one launch of each kernel for counter collection (a 1 GiB "
+                         "calibration copy, a cold batch, a warm 3-pass batch, one full "
+                         "assignment) and exit")
     return ap.parse_args()
 
 
@@ -70,6 +74,10 @@ def main():
           file=sys.stderr, flush=True)
     m, d = X.shape
     W, s, k = args.workers, args.s, args.k
+    prec = api.PREC_BF16_MFMA if args.precision == "bf16" else api.PREC_FP32
+    if args.pmc_target:
+        pmc_target(api, X, m, d, W, s, k, prec, args.seed)
+        return
 
     C_inc = torch.full((W, k, d), float("nan"), dtype=torch.float32, device=dev)
     f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device=dev)
@@ -79,7 +87,6 @@ def main():
     counts = torch.empty(k, dtype=torch.int64, device=dev)
     sse = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    prec = api.PREC_BF16_MFMA if args.precision == "bf16" else api.PREC_FP32
 
     ev = {name: [] for name in ("lloyd", "assign")}
 
@@ -166,6 +173,30 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def pmc_target(api, X, m, d, W, s, k, prec, seed):
+    """One launch of each kernel, for hardware-counter collection: a 1 GiB
+    device copy whose counter readings calibrate the traffic counters, a
+    cold batch (K-means++ seeding and passes to the stop rule), a warm batch
+    of exactly 3 passes, and one full assignment."""
+    import torch
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device=X.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    desc, idx_len, c_len = api.make_desc([s] * W, [k] * W, seed=seed, sample_id=range(W), d=d)
+    idx = api.draw_samples(m, desc, idx_len)
+    C = torch.full((c_len,), float("nan"), device=X.device)
+    api.lloyd_batch(X, idx, desc, C, precision=prec)
+    desc2, _, _ = api.make_desc([s] * W, [k] * W, seed=seed, sample_id=range(W, 2 * W), d=d)
+    idx2 = api.draw_samples(m, desc2, idx_len)
+    api.lloyd_batch(X, idx2, desc2, C, max_iter=3, rel_tol=0.0, precision=prec)
+    api.assign_sse(X, C[: k * d].view(k, d).contiguous(), precision=prec)
+    torch.cuda.synchronize()
+    print("[bench] pmc target done", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
