@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="MFMA type of the distance screening (decisions are FP64-exact)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the default launch configuration instead of autotuning")
     ap.add_argument("--pmc-target", action="store_true",
                     help="run one launch of each kernel for counter collection (a 1 GiB "
                          "calibration copy, a cold batch, a warm 3-pass batch, one full "
@@ -83,34 +85,51 @@ def main():
     f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device=dev)
     C = torch.empty_like(C_inc)
     idx = torch.empty(W * s, dtype=torch.int64, device=dev)
+    f = torch.empty(W, dtype=torch.float64, device=dev)
+    it = torch.empty(W, dtype=torch.int32, device=dev)
     labels = torch.empty(m, dtype=torch.int32, device=dev)
     counts = torch.empty(k, dtype=torch.int64, device=dev)
     sse = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
+    # one plan for every round: descriptors uploaded once, sample ids
+    # advanced on the device; its launch configuration is autotuned (warm
+    # passes on a throwaway round) before anything is timed
+    desc, idx_len, c_len = api.make_desc([s] * W, [k] * W, seed=args.seed, sample_id=range(W), d=d)
+    plan = api.Plan(d, desc, idx_len, c_len, precision=prec)
+    tune = {}
+    if args.autotune:
+        from paper_2311_04517_amd import tuning
+
+        plan.draw(m, idx)
+        Ct = torch.full((c_len,), float("nan"), device=dev)
+        plan.lloyd(X, idx, Ct)  # converged start, so the timed passes are warm ones
+        tune, ms = tuning.tuned(plan, X, idx, Ct, max_iter=3, retune=True)
+        print(f"[bench] autotuned {tune} ({ms:.3f} ms for 3 passes)", file=sys.stderr, flush=True)
+        del Ct
+
     ev = {name: [] for name in ("lloyd", "assign")}
 
     def step(r, timed):
-        ids = [r * W + w for w in range(W)]
-        desc, idx_len, _ = api.make_desc([s] * W, [k] * W, seed=args.seed, sample_id=ids, d=d)
-        api.draw_samples(m, desc, idx_len, out=idx)
+        plan.draw(m, idx)
         C.copy_(C_inc)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        f, it, _ = api.lloyd_batch(X, idx, desc, C, precision=prec)
+        plan.lloyd(X, idx, C, f_out=f, iters_out=it)
         e1.record(stream)
         api.keep_best(C, f, C_inc, f_inc, k, d)
+        plan.advance(W)
         Cb, fb, wb = api.select_best(C_inc, f_inc, k, d)
         e2.record(stream)
         api.assign_sse(X, Cb, labels=labels, counts=counts, sse=sse, precision=prec)
-        e3 = torch.cuda.Event(enable_timing=True)
         e3.record(stream)
         if timed:
             ev["lloyd"].append((e0, e1))
             ev["assign"].append((e2, e3))
-        return it, idx.clone() if r == 0 else None
+        return it.clone()
 
     r = 0
     for _ in range(args.warmup):
@@ -125,8 +144,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        it, _ = step(r, True)
-        its.append(it)
+        its.append(step(r, True))
         r += 1
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -165,7 +183,7 @@ def main():
                    "passes_per_step": float(passes.mean())},
         "roofline": {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_lloyd_resident<32,256,{prec}>",
+                     "kernel": f"k_lloyd_resident<32,256,{prec}>", "launch": tune,
                      "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
                      "avg_launch_ms": t_lloyd * 1e3},
         "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,

@@ -52,11 +52,15 @@ typedef enum {
     HPC_ERR_UNSUPPORTED = -4  /* valid request outside what this build handles */
 } hpc_status;
 
-/* Arithmetic of the point-to-centroid distance in the assignment step. */
+/* Arithmetic that SCREENS the nearest centroid in the assignment step.  In
+ * both modes the scores |c|^2 - 2 x.c are computed on the matrix cores and
+ * the winner is accepted only when its lead over the runner-up exceeds a
+ * rigorous bound on the screening error; any other point is re-decided with
+ * FP64 distances.  Every decided index is therefore the one FP64 distances
+ * give (lowest index on exact ties); the mode changes speed only. */
 enum {
-    HPC_PREC_FP32 = 0,     /* FP32 direct differences                          */
-    HPC_PREC_BF16_MFMA = 1 /* BF16 cross term on MFMA, FP32 re-check of near
-                              ties (see hpc_lloyd_batch)                       */
+    HPC_PREC_FP32 = 0,     /* FP32 operands, MFMA 16x16x4 f32                  */
+    HPC_PREC_BF16_MFMA = 1 /* BF16 operands, MFMA 16x16x32 bf16, FP32 accumulate */
 };
 
 /* One sample of a batch.  idx_offset: first entry of this sample in the idx
@@ -116,7 +120,7 @@ int hpc_draw_samples(int64_t m, const hpc_sample_desc *desc, int32_t n_samples, 
  *   chosen (device int32[k], nullable): sample-local index of the point given
  *     to each seeded row, -1 for kept rows.
  *   Stream: tag 1, counter (block, sample_id, call_id, 0).
- * Distances are FP32; prefix sums and potentials FP64.
+ * Distances, prefix sums and potentials are FP64.
  * Errors: NULL X/idx/C, s < k, n_candidates outside [1, 4], sizes out of
  * range. */
 int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, int32_t s,
@@ -140,10 +144,8 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  * the last pass at labels_out + desc[b].idx_offset.
  *   desc: HOST array of n_samples entries (validated against idx_len and
  *     c_len, the lengths of idx and C).
- *   precision: HPC_PREC_FP32, or HPC_PREC_BF16_MFMA (cross term in BF16 on
- *     MFMA with FP32 accumulation; a point whose two best scores are closer
- *     than the rounding bound is re-evaluated with FP32 direct differences,
- *     so labels equal those of the FP32 path).
+ *   precision: HPC_PREC_FP32 or HPC_PREC_BF16_MFMA (screening type, see
+ *     above; labels, f and centroids do not depend on it).
  *   f_out (device double[n]), iters_out (device int32[n]); labels_out
  *   nullable (device int32[idx_len]).
  * Samples may be processed in any order and concurrently; each sample's
@@ -175,13 +177,210 @@ int hpc_select_best(const float *C_inc, const double *f_inc, int32_t n_workers, 
  *     on ties); counts (device int64[k], nullable): points per centroid;
  *   sse (device double[1]): sum_i min_j |x_i - c_j|^2, accumulated in FP64
  *     in a fixed order (bitwise reproducible for a fixed launch shape).
- *   precision: as in hpc_lloyd_batch; the objective is always the FP32
+ *   precision: as in hpc_lloyd_batch; the objective is always the FP64
  *     direct-difference distance to the chosen centroid summed in FP64.
  * Errors: NULL X/C/sse, m < 1, sizes out of range, every row degenerate is
  * NOT detected (sse is then +inf and labels -1). */
 int hpc_assign_sse(const float *X, int64_t m, int32_t d, const float *C, int32_t k,
                    int32_t precision, int32_t *labels, int64_t *counts, double *sse,
                    void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batch plans: a fixed table of uneven samples prepared once, run many times
+ * (Algorithm 3's worker loop over B workers, each sample with its own s and
+ * k).  Creating a plan validates the descriptors, orders the samples longest
+ * first (work ~ s*k), and allocates every device buffer a run needs (the
+ * descriptor table, the gathered samples, D^2, the work queue), so running
+ * it enqueues kernel launches only: no allocation, no host copy, no
+ * synchronisation.  That makes a run capturable in a HIP graph; the library
+ * captures one worker-loop round itself (hpc_plan_capture_round) and replays
+ * it with one graph launch per round.
+ * ------------------------------------------------------------------------ */
+typedef struct hpc_plan_s *hpc_plan;
+
+/* Launch configuration of the resident Lloyd kernel (one workgroup of 256
+ * threads per sample at a time, persistent grid pulling samples from a
+ * queue).  Every configuration computes the same labels, pass counts and
+ * centroids up to FP64 summation order. */
+typedef struct {
+    int32_t wg_per_cu; /* resident workgroups per compute unit; 0 = as many
+                          as the occupancy allows                          */
+    int32_t copies;    /* private FP64 partial-sum copies per workgroup, 1..4
+                          (one per wave removes LDS atomic contention
+                          between waves); 0 = as many as fit in 64 KiB     */
+    int32_t order;     /* 0: longest sample first; 1: descriptor order      */
+    int32_t reserved;  /* must be 0                                         */
+} hpc_tune;
+
+/* Create a plan on the current device for n_samples samples (desc: HOST
+ * array, validated as in hpc_lloyd_batch against idx_len and c_len, copied;
+ * 1 <= n_samples <= 65535) of d-dimensional data, screening precision
+ * `precision`.  The plan owns its device memory (about idx_len * (4*pad(d)
+ * + 8) bytes, pad(d) the next of 8, 16, 32, 64, 128) until
+ * hpc_plan_destroy.  *out receives the handle (NULL on error).  The default
+ * configuration is {0, 0, 0, 0}. */
+int hpc_plan_create(int32_t d, const hpc_sample_desc *desc, int32_t n_samples, int64_t idx_len,
+                    int64_t c_len, int32_t precision, hpc_plan *out);
+
+/* Destroy a plan after synchronising the device work that uses it; frees
+ * its memory and its captured graph.  NULL is a no-op. */
+int hpc_plan_destroy(hpc_plan plan);
+
+/* Set / read the launch configuration.  Errors: wg_per_cu < 0, copies
+ * outside [0, 4], order outside {0, 1}, reserved != 0, or a configuration
+ * whose LDS does not fit.  A captured round keeps the configuration it was
+ * captured with. */
+int hpc_plan_set_tune(hpc_plan plan, const hpc_tune *tune);
+int hpc_plan_get_tune(hpc_plan plan, hpc_tune *tune);
+
+/* Cache key of the plan's tuning problem (device architecture, padded d,
+ * precision, and power-of-two buckets of n_samples, the largest k and the
+ * mean s), NUL-terminated into buf (host, len bytes). */
+int hpc_plan_tune_key(hpc_plan plan, char *buf, int32_t len);
+
+/* Autotuner: times every configuration (copies in {1, 2, 4} x wg_per_cu
+ * from 1 to the occupancy limit x both orders when the samples are uneven)
+ * on the caller's inputs -- hpc_plan_lloyd from a copy of C, max_iter
+ * passes, no early stop -- keeps the fastest (HIP-event time, best of two)
+ * as the plan's configuration and returns it in *best (host) and its time
+ * in *best_ms (host, nullable).  C is not modified.  SYNCHRONOUS: returns
+ * after the timing runs on hip_stream have finished. */
+int hpc_plan_autotune(hpc_plan plan, const float *X, int64_t m, const int64_t *idx,
+                      const float *C, int32_t max_iter, hpc_tune *best, double *best_ms,
+                      void *hip_stream);
+
+/* hpc_lloyd_batch on the plan's samples (same arithmetic, outputs and
+ * errors).  idx holds idx_len indices and C c_len floats, as at creation.
+ * Enqueues kernel launches only. */
+int hpc_plan_lloyd(hpc_plan plan, const float *X, int64_t m, const int64_t *idx, float *C,
+                   int32_t max_iter, double rel_tol, double *f_out, int32_t *iters_out,
+                   int32_t *labels_out, void *hip_stream);
+
+/* Draw every sample of the plan into idx (device int64[idx_len]) with the
+ * plan's current sample ids (as hpc_draw_samples).  Kernel launch only. */
+int hpc_plan_draw(hpc_plan plan, int64_t m, int64_t *idx, void *hip_stream);
+
+/* sample_id += id_stride for every sample in the plan's device table (the
+ * ids the next draw and the next re-seeding use).  Kernel launch only. */
+int hpc_plan_advance(hpc_plan plan, uint64_t id_stride, void *hip_stream);
+
+/* One round of the worker loop (Algorithm 3) for every sample b of the plan:
+ *   draw the sample (as hpc_draw_samples, stream (seed_b, sample_id_b));
+ *   C_b <- C_inc_b; Lloyd on the sample (as hpc_plan_lloyd);
+ *   keep the best: if f_out[b] < f_inc[b] then C_inc_b <- C_b, f_inc[b] <-
+ *     f_out[b];
+ *   sample_id_b += id_stride in the plan's device table (so the next round
+ *     draws fresh samples; 0 repeats the same samples).
+ * idx: device int64[idx_len] (overwritten); C, C_inc: device float[c_len];
+ * f_inc: device double[n_samples] (+inf = no incumbent yet; C_inc rows NaN
+ * = degenerate, so the first round seeds by K-means++).  Enqueues kernel
+ * launches only. */
+int hpc_plan_round(hpc_plan plan, const float *X, int64_t m, int64_t *idx, float *C, float *C_inc,
+                   double *f_inc, int32_t max_iter, double rel_tol, double *f_out,
+                   int32_t *iters_out, uint64_t id_stride, void *hip_stream);
+
+/* Capture hpc_plan_round with these arguments into a HIP graph held by the
+ * plan (replacing any earlier one).  Nothing runs; the buffers must stay
+ * valid while the graph is replayed.  The capture uses a private stream, so
+ * any caller stream may replay it. */
+int hpc_plan_capture_round(hpc_plan plan, const float *X, int64_t m, int64_t *idx, float *C,
+                           float *C_inc, double *f_inc, int32_t max_iter, double rel_tol,
+                           double *f_out, int32_t *iters_out, uint64_t id_stride);
+
+/* Replay the captured round n_rounds times on hip_stream (one graph launch
+ * each).  Errors: no captured round, n_rounds < 0. */
+int hpc_plan_replay(hpc_plan plan, int32_t n_rounds, void *hip_stream);
+
+/* Restore the plan's device descriptor table to the descriptors given at
+ * creation (undoing the sample_id advances of earlier rounds).  Enqueued on
+ * hip_stream from the plan's own device copy. */
+int hpc_plan_reset_ids(hpc_plan plan, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learned initializer.  A set encoder proposes the k starting centroids of
+ * a cold sample from the sample itself, as an alternative to the K-means++
+ * seeding of Section 3; the proposal is used only where its sample
+ * objective (Eq. (1) on the sample) is no larger than the seeding's.
+ *
+ *   mu = mean of the encoder's points, sigma = sqrt(mean |x - mu|^2)
+ *   x~ = (x - mu) / sigma
+ *   h1 = relu(x~ W1 + b1)  (d -> 256),  h2 = relu(h1 W2 + b2)  (256 -> 256)
+ *   p = mean of h2 over the points;  o = p Wh + bh  (256 -> k*d)
+ *   proposal row r, column q = mu_q + sigma * o[r*d + q]
+ *
+ * The encoder reads the first n_b = min(s, n_enc) points of each sample
+ * (the points of a sample are i.i.d., so these are a uniform subsample).
+ * Parameters are FP32 masters laid out flat in the order W1 (d x 256), b1,
+ * W2 (256 x 256), b2, Wh (256 x k*d), bh, matrices row-major; the kernels
+ * use the weights rounded to BF16 (matrix cores, FP32 accumulation).
+ * Training minimises the symmetric nearest-neighbour (Chamfer) distance
+ * between o and the target centroids T in normalised coordinates:
+ *   L = mean over samples of (1/k) sum_j min_l |o_j - T~_l|^2
+ *                          + (1/k) sum_l min_j |o_j - T~_l|^2,
+ * T~ = (T - mu) / sigma, with Adam (lr given, betas 0.9 / 0.999, eps 1e-8).
+ * A model is used from one stream at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct hpc_setenc_s *hpc_setenc;
+
+/* Create a model for d-dimensional data (1 <= d <= 32) and k centroids
+ * (1 <= k <= 64) that reads n_enc points per sample (16 <= n_enc <= 2^20)
+ * and trains on at most max_batch samples per gradient call (training
+ * scratch ~ 3 KiB per point: max_batch * n_enc * (3*256 + 32) floats).
+ * Initial weights: uniform He initialisation from Philox (tag 4, key
+ * seed).  SYNCHRONOUS. */
+int hpc_setenc_create(int32_t d, int32_t k, int32_t n_enc, int32_t max_batch, uint64_t seed,
+                      hpc_setenc *out);
+
+/* Destroy a model (synchronises the device).  NULL is a no-op. */
+int hpc_setenc_destroy(hpc_setenc model);
+
+/* Number of FP32 parameters (host int64 out). */
+int hpc_setenc_param_count(hpc_setenc model, int64_t *n_params);
+
+/* Copy the parameters to / from HOST memory (param_count floats, layout
+ * above).  rounded != 0 returns the weights as the kernels use them (BF16
+ * round-to-nearest-even).  set_params keeps the Adam state.  SYNCHRONOUS. */
+int hpc_setenc_get_params(hpc_setenc model, int32_t rounded, float *host);
+int hpc_setenc_set_params(hpc_setenc model, const float *host);
+
+/* Copy the gradient of the last hpc_setenc_grad call to HOST memory.
+ * SYNCHRONOUS. */
+int hpc_setenc_get_grads(hpc_setenc model, float *host);
+
+/* Proposals for a batch: for every sample b (desc: HOST array, every
+ * desc[b].k equal to the model's k), the k x d proposal is written at
+ * C + desc[b].c_offset.  idx / C: device arrays of idx_len / c_len. */
+int hpc_setenc_propose(hpc_setenc model, const float *X, int64_t m, const int64_t *idx,
+                       int64_t idx_len, const hpc_sample_desc *desc, int32_t n_samples, float *C,
+                       int64_t c_len, void *hip_stream);
+
+/* Loss and gradient of a batch of at most max_batch samples against the
+ * target centroids T (device, the k x d block of sample b at
+ * T + desc[b].c_offset).  loss: device double[1], nullable. */
+int hpc_setenc_grad(hpc_setenc model, const float *X, int64_t m, const int64_t *idx,
+                    int64_t idx_len, const hpc_sample_desc *desc, int32_t n_samples,
+                    const float *T, int64_t c_len, double *loss, void *hip_stream);
+
+/* One Adam step with the last gradient (bias-corrected; step count kept
+ * by the model). */
+int hpc_setenc_adam(hpc_setenc model, float lr, void *hip_stream);
+
+/* Seeding of a cold batch with the learned proposal where it is at least as
+ * good: for every sample b,
+ *   P = the model's proposal;
+ *   K = the K-means++ seeding a cold start of hpc_lloyd_batch makes (all
+ *       rows degenerate, re-seeding stream tag 2, call_id 0);
+ *   f_prop[b] = f(P, S), f_kpp[b] = f(K, S) (one assignment pass each);
+ *   C_b <- P if f_prop[b] <= f_kpp[b], else K;  accepted[b] = 1 / 0.
+ * C receives the chosen seeds (all rows valid), C_kpp the K-means++
+ * seeding (device float[c_len] each); f_prop / f_kpp device double[n];
+ * accepted device int32[n], nullable.  Lloyd from C then continues as from
+ * any start (hpc_lloyd_batch); where K is chosen, that run is the cold
+ * start's run. */
+int hpc_learned_seed(hpc_setenc model, const float *X, int64_t m, const int64_t *idx,
+                     int64_t idx_len, const hpc_sample_desc *desc, int32_t n_samples, float *C,
+                     float *C_kpp, int64_t c_len, int32_t precision, double *f_prop,
+                     double *f_kpp, int32_t *accepted, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,20 @@ class SampleDesc(ct.Structure):
     ]
 
 
+class Tune(ct.Structure):
+    """Mirror of ``hpc_tune``."""
+
+    _fields_ = [
+        ("wg_per_cu", ct.c_int32),
+        ("copies", ct.c_int32),
+        ("order", ct.c_int32),
+        ("reserved", ct.c_int32),
+    ]
+
+    def as_dict(self):
+        return {"wg_per_cu": self.wg_per_cu, "copies": self.copies, "order": self.order}
+
+
 class HpcError(RuntimeError):
     def __init__(self, code: int, where: str, msg: str):
         super().__init__(f"{where}: status {code}: {msg}")
@@ -60,6 +74,31 @@ _SIGS = {
     "hpc_keep_best": ([_p, _p, _p, _p, _i32, _i32, _i32, _p, _p], ct.c_int),
     "hpc_select_best": ([_p, _p, _i32, _i32, _i32, _p, _p, _p, _p], ct.c_int),
     "hpc_assign_sse": ([_p, _i64, _i32, _p, _i32, _i32, _p, _p, _p, _p], ct.c_int),
+    "hpc_plan_create": ([_i32, _p, _i32, _i64, _i64, _i32, ct.POINTER(_p)], ct.c_int),
+    "hpc_plan_destroy": ([_p], ct.c_int),
+    "hpc_plan_set_tune": ([_p, _p], ct.c_int),
+    "hpc_plan_get_tune": ([_p, _p], ct.c_int),
+    "hpc_plan_tune_key": ([_p, ct.c_char_p, _i32], ct.c_int),
+    "hpc_plan_autotune": ([_p, _p, _i64, _p, _p, _i32, _p, _p, _p], ct.c_int),
+    "hpc_plan_lloyd": ([_p, _p, _i64, _p, _p, _i32, _f64, _p, _p, _p, _p], ct.c_int),
+    "hpc_plan_draw": ([_p, _i64, _p, _p], ct.c_int),
+    "hpc_plan_advance": ([_p, _u64, _p], ct.c_int),
+    "hpc_plan_round": ([_p, _p, _i64, _p, _p, _p, _p, _i32, _f64, _p, _p, _u64, _p], ct.c_int),
+    "hpc_plan_capture_round": ([_p, _p, _i64, _p, _p, _p, _p, _i32, _f64, _p, _p, _u64],
+                               ct.c_int),
+    "hpc_plan_replay": ([_p, _i32, _p], ct.c_int),
+    "hpc_plan_reset_ids": ([_p, _p], ct.c_int),
+    "hpc_setenc_create": ([_i32, _i32, _i32, _i32, _u64, ct.POINTER(_p)], ct.c_int),
+    "hpc_setenc_destroy": ([_p], ct.c_int),
+    "hpc_setenc_param_count": ([_p, ct.POINTER(_i64)], ct.c_int),
+    "hpc_setenc_get_params": ([_p, _i32, _p], ct.c_int),
+    "hpc_setenc_set_params": ([_p, _p], ct.c_int),
+    "hpc_setenc_get_grads": ([_p, _p], ct.c_int),
+    "hpc_setenc_propose": ([_p, _p, _i64, _p, _i64, _p, _i32, _p, _i64, _p], ct.c_int),
+    "hpc_setenc_grad": ([_p, _p, _i64, _p, _i64, _p, _i32, _p, _i64, _p, _p], ct.c_int),
+    "hpc_setenc_adam": ([_p, ct.c_float, _p], ct.c_int),
+    "hpc_learned_seed": ([_p, _p, _i64, _p, _i64, _p, _i32, _p, _p, _i64, _i32, _p, _p, _p, _p],
+                         ct.c_int),
 }
 
 

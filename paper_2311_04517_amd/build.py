@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhpclust.so")
-SOURCES = [os.path.join(CSRC, "hpclust.hip")]
+SOURCES = [os.path.join(CSRC, "hpclust.hip"), os.path.join(CSRC, "setenc.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
 HEADERS.append(os.path.join(ROOT, "include", "hpclust.h"))
 

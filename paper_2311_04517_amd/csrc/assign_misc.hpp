@@ -235,4 +235,42 @@ __global__ __launch_bounds__(NT) void k_select_best(const float* __restrict__ C_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Per-descriptor forms of the worker-loop bookkeeping (Algorithm 3), for a
+// batch whose samples have their own k: sample b's centroid block is the k_b
+// x d floats at desc[b].c_offset in both C and the incumbent array.
+// ---------------------------------------------------------------------------
+
+// C <- C_inc for every sample (the round starts from the incumbents).
+// grid.y = sample.
+__global__ void k_copy_blocks(const hpc_sample_desc* __restrict__ desc, int32_t d,
+                              const float* __restrict__ src, float* __restrict__ dst) {
+    const hpc_sample_desc ds = desc[blockIdx.y];
+    const int64_t n = (int64_t)ds.k * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        dst[ds.c_offset + e] = src[ds.c_offset + e];
+}
+
+// Keep the best: one workgroup per sample; strict < as in k_keep_best.
+__global__ void k_keep_best_desc(const hpc_sample_desc* __restrict__ desc, int32_t d,
+                                 const float* __restrict__ C_new, const double* __restrict__ f_new,
+                                 float* __restrict__ C_inc, double* __restrict__ f_inc) {
+    const int b = blockIdx.x;
+    const hpc_sample_desc ds = desc[b];
+    const double fn = f_new[b], fi = f_inc[b];
+    const bool take = fn < fi;
+    if (take)
+        for (int64_t e = threadIdx.x; e < (int64_t)ds.k * d; e += blockDim.x)
+            C_inc[ds.c_offset + e] = C_new[ds.c_offset + e];
+    __syncthreads();
+    if (threadIdx.x == 0 && take) f_inc[b] = fn;
+}
+
+// Next round's samples: sample_id += stride for every descriptor.
+__global__ void k_advance_ids(hpc_sample_desc* __restrict__ desc, int32_t n, uint64_t stride) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) desc[b].sample_id += stride;
+}
+
 }  // namespace hpc

@@ -12,18 +12,21 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "../../include/hpclust.h"
 #include "assign_misc.hpp"
 #include "common.hpp"
+#include "host_util.hpp"
 #include "lloyd_resident.hpp"
 
 namespace {
-
 thread_local std::string g_last_error = "";
+}  // namespace
 
+namespace hpc_host {
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -33,13 +36,11 @@ int fail(int code, const char* fmt, ...) {
     g_last_error = buf;
     return code;
 }
+}  // namespace hpc_host
 
-#define HPC_HIP(call)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (call);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(HPC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
-    } while (0)
+namespace {
+
+using hpc_host::fail;
 
 constexpr int kMaxD = 128;
 constexpr int kNT = 256;  // threads per workgroup of the resident kernels
@@ -155,26 +156,60 @@ int max_dyn_lds(int* bytes) {
     return HPC_OK;
 }
 
+// Call f(integral_constant<int, D>, integral_constant<int, PREC>) for the
+// padded dimension D and the precision mode.
+template <class F>
+int with_dp(int D, int prec, F&& f) {
+    using std::integral_constant;
+    const bool bf = prec == HPC_PREC_BF16_MFMA;
+#define HPC_DP(DD)                                                                 \
+    case DD:                                                                       \
+        return bf ? f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecBF16>{}) \
+                  : f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecF32>{})
+    switch (D) {
+        HPC_DP(8);
+        HPC_DP(16);
+        HPC_DP(32);
+        HPC_DP(64);
+        HPC_DP(128);
+    }
+#undef HPC_DP
+    return fail(HPC_ERR_UNSUPPORTED, "padded dimension %d", D);
+}
+
 // --------------------------------------------------------------------------
 // Resident Lloyd / seeding launch.
 // --------------------------------------------------------------------------
+struct ResGeo {
+    int grid = 1;        // workgroups launched
+    int copies = 1;      // private partial-sum copies per workgroup
+    size_t lds = 0;      // dynamic LDS bytes
+    int per_cu_max = 0;  // occupancy limit at this LDS size
+};
+
+// Launch geometry for a batch of n_wg samples with at most kmax centroids.
+// copies_req 0 = as many private copies as fit in 64 KiB; wg_per_cu 0 = as
+// many workgroups per CU as the occupancy allows.
 template <int D, int PREC>
-int launch_resident(hpc::LloydArgs a, int n_wg, hipStream_t st) {
+int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo* out) {
     using S = hpc::Smem<D, kNT, PREC>;
     constexpr int NW = kNT / hpc::kWave;
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
     if (rc) return rc;
-    // as many private partial-sum copies as fit (one per wave = no atomics)
     int copies = NW;
-    const size_t soft = 64 * 1024;
-    while (copies > 1 && S::bytes(a.kmax, copies) > soft) --copies;
-    size_t lds = S::bytes(a.kmax, copies);
+    if (copies_req > 0) {
+        copies = std::min(copies_req, NW);
+    } else {
+        const size_t soft = 64 * 1024;
+        while (copies > 1 && S::bytes(kmax, copies) > soft) --copies;
+    }
+    const size_t lds = S::bytes(kmax, copies);
     if (lds > (size_t)lds_max)
         return fail(HPC_ERR_UNSUPPORTED,
-                    "k=%d with padded d=%d needs %zu bytes of LDS per workgroup (limit %d)",
-                    a.kmax, D, lds, lds_max);
-    a.n_copies = copies;
+                    "k=%d with padded d=%d and %d partial copies needs %zu bytes of LDS per "
+                    "workgroup (limit %d)",
+                    kmax, D, copies, lds, lds_max);
     auto kern = hpc::k_lloyd_resident<D, kNT, PREC>;
     if (lds > 64 * 1024)
         HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -184,28 +219,33 @@ int launch_resident(hpc::LloydArgs a, int n_wg, hipStream_t st) {
     int cus = 0;
     rc = device_cus(&cus);
     if (rc) return rc;
-    int grid = std::max(1, std::min(n_wg, cus * std::max(1, per_cu)));
+    per_cu = std::max(1, per_cu);
+    const int use = wg_per_cu > 0 ? std::min(per_cu, wg_per_cu) : per_cu;
+    out->grid = std::max(1, std::min(n_wg, cus * use));
+    out->copies = copies;
+    out->lds = lds;
+    out->per_cu_max = per_cu;
+    return HPC_OK;
+}
+
+// Enqueue the queue reset and the resident kernel (kernel launches only).
+template <int D, int PREC>
+int launch_resident(hpc::LloydArgs a, const ResGeo& g, hipStream_t st) {
+    a.n_copies = g.copies;
     hipLaunchKernelGGL(hpc::k_fill_i32, dim3(1), dim3(64), 0, st, a.queue, (int64_t)1, 0);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
+    hipLaunchKernelGGL((hpc::k_lloyd_resident<D, kNT, PREC>), dim3(g.grid), dim3(kNT), g.lds, st,
+                       a);
     HPC_HIP(hipGetLastError());
     return HPC_OK;
 }
 
 int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, int n_wg, hipStream_t st) {
-    const bool bf = prec == HPC_PREC_BF16_MFMA;
-    switch (D) {
-        case 8: return bf ? launch_resident<8, hpc::kPrecBF16>(a, n_wg, st)
-                          : launch_resident<8, hpc::kPrecF32>(a, n_wg, st);
-        case 16: return bf ? launch_resident<16, hpc::kPrecBF16>(a, n_wg, st)
-                           : launch_resident<16, hpc::kPrecF32>(a, n_wg, st);
-        case 32: return bf ? launch_resident<32, hpc::kPrecBF16>(a, n_wg, st)
-                           : launch_resident<32, hpc::kPrecF32>(a, n_wg, st);
-        case 64: return bf ? launch_resident<64, hpc::kPrecBF16>(a, n_wg, st)
-                           : launch_resident<64, hpc::kPrecF32>(a, n_wg, st);
-        case 128: return bf ? launch_resident<128, hpc::kPrecBF16>(a, n_wg, st)
-                            : launch_resident<128, hpc::kPrecF32>(a, n_wg, st);
-    }
-    return fail(HPC_ERR_UNSUPPORTED, "padded dimension %d", D);
+    return with_dp(D, prec, [&](auto Dc, auto Pc) {
+        ResGeo g;
+        int rc = resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(a.kmax, n_wg, 0, 0, &g);
+        if (rc) return rc;
+        return launch_resident<decltype(Dc)::value, decltype(Pc)::value>(a, g, st);
+    });
 }
 
 template <int D, int PREC>
@@ -281,6 +321,16 @@ int check_desc(const hpc_sample_desc* desc, int32_t n, int64_t idx_len, int64_t 
     return HPC_OK;
 }
 
+// Longest-first processing order (work ~ s * k), ties by descriptor order.
+std::vector<int32_t> longest_first(const hpc_sample_desc* desc, int32_t n) {
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (int64_t)desc[a].s * desc[a].k > (int64_t)desc[b].s * desc[b].k;
+    });
+    return order;
+}
+
 // Run the resident kernel over a batch (Lloyd, or seeding only).
 int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64_t idx_len,
                  const hpc_sample_desc* desc, int32_t n, float* C, int32_t max_iter,
@@ -291,12 +341,7 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     int rc = get_ws(st, &w);
     if (rc) return rc;
     const int D = pad_dim(d);
-    // longest first: work ~ s * k
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return (int64_t)desc[a].s * desc[a].k > (int64_t)desc[b].s * desc[b].k;
-    });
+    const std::vector<int32_t> order = longest_first(desc, n);
     const size_t desc_b = (size_t)n * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n * 4;
     const size_t sbuf_b = (size_t)idx_len * D * 4;
@@ -337,6 +382,132 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     a.chosen = chosen;
     a.vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
     return dispatch_resident(D, precision, a, n, st);
+}
+
+int next_pow2(int64_t v) {
+    int e = 0;
+    while (((int64_t)1 << e) < v) ++e;
+    return e;
+}
+
+}  // namespace
+
+// A prepared batch (include/hpclust.h, "Batch plans").  All device buffers
+// live in one allocation.
+struct hpc_plan_s {
+    int device = 0;
+    int32_t d = 0, D = 0, prec = 0, n = 0, kmax = 0;
+    int64_t idx_len = 0, c_len = 0;
+    std::vector<hpc_sample_desc> desc;
+    char* mem = nullptr;
+    hpc_sample_desc* desc_dev = nullptr;   // live table (sample ids advance)
+    hpc_sample_desc* desc_init = nullptr;  // table as created
+    int32_t* order_dev = nullptr;          // [0, n): longest first; [n, 2n): given order
+    int32_t* queue = nullptr;
+    float* sbuf = nullptr;
+    double* d2 = nullptr;
+    float* tC = nullptr;  // autotuner scratch
+    double* tf = nullptr;
+    int32_t* tit = nullptr;
+    hpc_tune tune{};
+    ResGeo geo;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int plan_check(hpc_plan p, const char* where) {
+    if (!p) return fail(HPC_ERR_INVALID_ARG, "%s: NULL plan", where);
+    int dev = 0;
+    HPC_HIP(hipGetDevice(&dev));
+    if (dev != p->device)
+        return fail(HPC_ERR_INVALID_ARG, "%s: plan was created on device %d, current is %d", where,
+                    p->device, dev);
+    return HPC_OK;
+}
+
+int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g) {
+    return with_dp(p->D, p->prec, [&](auto Dc, auto Pc) {
+        return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(p->kmax, p->n,
+                                                                           t.wg_per_cu, t.copies, g);
+    });
+}
+
+hpc::LloydArgs plan_args(hpc_plan p, const float* X, int64_t m, const int64_t* idx, float* C,
+                         int32_t max_iter, double rel_tol, double* f_out, int32_t* iters_out,
+                         int32_t* labels_out, int order) {
+    hpc::LloydArgs a{};
+    a.X = X;
+    a.m = m;
+    a.d = p->d;
+    a.idx = idx;
+    a.desc = p->desc_dev;
+    a.order = p->order_dev + (order ? p->n : 0);
+    a.n_samples = p->n;
+    a.C = C;
+    a.max_iter = max_iter;
+    a.rel_tol = rel_tol;
+    a.f_out = f_out;
+    a.iters_out = iters_out;
+    a.labels_out = labels_out;
+    a.sbuf = p->sbuf;
+    a.d2buf = p->d2;
+    a.queue = p->queue;
+    a.kmax = p->kmax;
+    a.n_cand = 3;
+    a.vec4 = (p->d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    return a;
+}
+
+int plan_launch(hpc_plan p, const hpc::LloydArgs& a, const ResGeo& g, hipStream_t st) {
+    return with_dp(p->D, p->prec, [&](auto Dc, auto Pc) {
+        return launch_resident<decltype(Dc)::value, decltype(Pc)::value>(a, g, st);
+    });
+}
+
+int lloyd_opts_ok(const char* where, const float* X, int64_t m, const void* idx, const void* C,
+                  int32_t max_iter, double rel_tol, const void* f_out, const void* iters_out) {
+    if (!X || !idx || !C || !f_out || !iters_out)
+        return fail(HPC_ERR_INVALID_ARG, "%s: NULL pointer", where);
+    if (m < 1) return fail(HPC_ERR_INVALID_ARG, "%s: m < 1", where);
+    if (max_iter < 1 || !(rel_tol >= 0.0) || std::isinf(rel_tol))
+        return fail(HPC_ERR_INVALID_ARG, "%s: need max_iter>=1 and finite rel_tol>=0", where);
+    return HPC_OK;
+}
+
+void plan_draw(hpc_plan p, int64_t m, int64_t* idx, hipStream_t st) {
+    int64_t max_s = 0;
+    for (const auto& ds : p->desc) max_s = std::max<int64_t>(max_s, ds.s);
+    const int64_t nq = (max_s + 3) / 4;
+    const unsigned gx = (unsigned)std::min<int64_t>((nq + 255) / 256, 1024);
+    hipLaunchKernelGGL(hpc::k_draw_batch, dim3(gx, p->n), dim3(256), 0, st, m,
+                       (const hpc_sample_desc*)p->desc_dev, idx);
+}
+
+void plan_advance(hpc_plan p, uint64_t id_stride, hipStream_t st) {
+    hipLaunchKernelGGL(hpc::k_advance_ids, dim3((p->n + 255) / 256), dim3(256), 0, st, p->desc_dev,
+                       p->n, id_stride);
+}
+
+// Enqueue one worker-loop round (kernel launches only).
+int plan_enqueue_round(hpc_plan p, const float* X, int64_t m, int64_t* idx, float* C,
+                       float* C_inc, double* f_inc, int32_t max_iter, double rel_tol,
+                       double* f_out, int32_t* iters_out, uint64_t id_stride, hipStream_t st) {
+    plan_draw(p, m, idx, st);
+    const unsigned cx = (unsigned)std::min<int64_t>(((int64_t)p->kmax * p->d + 255) / 256, 64);
+    hipLaunchKernelGGL(hpc::k_copy_blocks, dim3(cx, p->n), dim3(256), 0, st,
+                       (const hpc_sample_desc*)p->desc_dev, p->d, (const float*)C_inc, C);
+    const hpc::LloydArgs a =
+        plan_args(p, X, m, idx, C, max_iter, rel_tol, f_out, iters_out, nullptr, p->tune.order);
+    int rc = plan_launch(p, a, p->geo, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(hpc::k_keep_best_desc, dim3(p->n), dim3(256), 0, st,
+                       (const hpc_sample_desc*)p->desc_dev, p->d, (const float*)C,
+                       (const double*)f_out, C_inc, f_inc);
+    if (id_stride) plan_advance(p, id_stride, st);
+    HPC_HIP(hipGetLastError());
+    return HPC_OK;
 }
 
 }  // namespace
@@ -502,6 +673,277 @@ int hpc_assign_sse(const float* X, int64_t m, int32_t d, const float* C, int32_t
     }
 #undef HPC_ASSIGN
     return fail(HPC_ERR_UNSUPPORTED, "hpc_assign_sse: d=%d", d);
+}
+
+int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, int64_t idx_len,
+                    int64_t c_len, int32_t precision, hpc_plan* out) {
+    if (!out) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_create: NULL out");
+    *out = nullptr;
+    if (!desc || d < 1 || d > kMaxD || n_samples < 1 || n_samples > 65535 || idx_len < 1 ||
+        c_len < 1)
+        return fail(HPC_ERR_INVALID_ARG,
+                    "hpc_plan_create: need desc, 1<=d<=%d, 1<=n_samples<=65535, idx_len>=1, "
+                    "c_len>=1",
+                    kMaxD);
+    if (precision != HPC_PREC_FP32 && precision != HPC_PREC_BF16_MFMA)
+        return fail(HPC_ERR_INVALID_ARG, "hpc_plan_create: unknown precision %d", precision);
+    int kmax = 0;
+    int rc = check_desc(desc, n_samples, idx_len, c_len, d, &kmax);
+    if (rc) return rc;
+    auto* p = new hpc_plan_s();
+    p->d = d;
+    p->D = pad_dim(d);
+    p->prec = precision;
+    p->n = n_samples;
+    p->kmax = kmax;
+    p->idx_len = idx_len;
+    p->c_len = c_len;
+    p->desc.assign(desc, desc + n_samples);
+    auto cleanup = [&](int code) {
+        if (p->mem) (void)hipFree(p->mem);
+        delete p;
+        return code;
+    };
+    if (hipGetDevice(&p->device) != hipSuccess)
+        return cleanup(fail(HPC_ERR_HIP, "hpc_plan_create: hipGetDevice failed"));
+    const size_t desc_b = (size_t)n_samples * sizeof(hpc_sample_desc);
+    const size_t order_b = (size_t)n_samples * 8;
+    const size_t sbuf_b = (size_t)idx_len * p->D * 4;
+    const size_t d2_b = (size_t)idx_len * 8;
+    const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)c_len * 4,
+                                     (size_t)n_samples * 8, (size_t)n_samples * 4});
+    hipError_t e = hipMalloc(&p->mem, need);
+    if (e != hipSuccess) {
+        p->mem = nullptr;
+        return cleanup(fail(HPC_ERR_NO_MEMORY, "hpc_plan_create: %zu bytes: %s", need,
+                            hipGetErrorString(e)));
+    }
+    Carve cv(p->mem);
+    p->desc_dev = static_cast<hpc_sample_desc*>(cv.take(desc_b));
+    p->desc_init = static_cast<hpc_sample_desc*>(cv.take(desc_b));
+    p->order_dev = static_cast<int32_t*>(cv.take(order_b));
+    p->queue = static_cast<int32_t*>(cv.take(256));
+    p->sbuf = static_cast<float*>(cv.take(sbuf_b));
+    p->d2 = static_cast<double*>(cv.take(d2_b));
+    p->tC = static_cast<float*>(cv.take((size_t)c_len * 4));
+    p->tf = static_cast<double*>(cv.take((size_t)n_samples * 8));
+    p->tit = static_cast<int32_t*>(cv.take((size_t)n_samples * 4));
+    std::vector<int32_t> orders = longest_first(desc, n_samples);
+    orders.resize((size_t)2 * n_samples);
+    std::iota(orders.begin() + n_samples, orders.end(), 0);
+    if (hipMemcpy(p->desc_dev, desc, desc_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->desc_init, desc, desc_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->order_dev, orders.data(), order_b, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(HPC_ERR_HIP, "hpc_plan_create: descriptor upload failed"));
+    rc = plan_geometry(p, p->tune, &p->geo);
+    if (rc) return cleanup(rc);
+    *out = p;
+    return HPC_OK;
+}
+
+int hpc_plan_destroy(hpc_plan plan) {
+    if (!plan) return HPC_OK;
+    int prev = 0;
+    HPC_HIP(hipGetDevice(&prev));
+    HPC_HIP(hipSetDevice(plan->device));
+    HPC_HIP(hipDeviceSynchronize());
+    if (plan->exec) HPC_HIP(hipGraphExecDestroy(plan->exec));
+    if (plan->cap) HPC_HIP(hipStreamDestroy(plan->cap));
+    if (plan->mem) HPC_HIP(hipFree(plan->mem));
+    delete plan;
+    HPC_HIP(hipSetDevice(prev));
+    return HPC_OK;
+}
+
+int hpc_plan_set_tune(hpc_plan plan, const hpc_tune* tune) {
+    int rc = plan_check(plan, "hpc_plan_set_tune");
+    if (rc) return rc;
+    if (!tune || tune->wg_per_cu < 0 || tune->copies < 0 || tune->copies > 4 || tune->order < 0 ||
+        tune->order > 1 || tune->reserved != 0)
+        return fail(HPC_ERR_INVALID_ARG,
+                    "hpc_plan_set_tune: need wg_per_cu>=0, copies in [0,4], order in {0,1}, "
+                    "reserved 0");
+    ResGeo g;
+    rc = plan_geometry(plan, *tune, &g);
+    if (rc) return rc;
+    plan->tune = *tune;
+    plan->geo = g;
+    return HPC_OK;
+}
+
+int hpc_plan_get_tune(hpc_plan plan, hpc_tune* tune) {
+    if (!plan || !tune) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_get_tune: NULL argument");
+    *tune = plan->tune;
+    return HPC_OK;
+}
+
+int hpc_plan_tune_key(hpc_plan plan, char* buf, int32_t len) {
+    if (!plan || !buf || len < 1) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_tune_key: bad argument");
+    hipDeviceProp_t prop;
+    HPC_HIP(hipGetDeviceProperties(&prop, plan->device));
+    int64_t sum_s = 0;
+    for (const auto& ds : plan->desc) sum_s += ds.s;
+    const int n = snprintf(buf, (size_t)len, "%s|d%d|p%d|n2^%d|k2^%d|s2^%d", prop.gcnArchName,
+                           plan->D, plan->prec, next_pow2(plan->n), next_pow2(plan->kmax),
+                           next_pow2((sum_s + plan->n - 1) / plan->n));
+    if (n < 0 || n >= len) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_tune_key: buffer too short");
+    return HPC_OK;
+}
+
+int hpc_plan_autotune(hpc_plan plan, const float* X, int64_t m, const int64_t* idx,
+                      const float* C, int32_t max_iter, hpc_tune* best, double* best_ms,
+                      void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_autotune");
+    if (rc) return rc;
+    rc = lloyd_opts_ok("hpc_plan_autotune", X, m, idx, C, max_iter, 0.0, plan->tf, plan->tit);
+    if (rc) return rc;
+    if (!best) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_autotune: NULL best");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    bool uneven = false;
+    for (const auto& ds : plan->desc)
+        uneven |= (int64_t)ds.s * ds.k != (int64_t)plan->desc[0].s * plan->desc[0].k;
+    std::vector<hpc_tune> cand;
+    for (int copies : {1, 2, 4}) {
+        hpc_tune t{0, copies, 0, 0};
+        ResGeo g;
+        if (plan_geometry(plan, t, &g) != HPC_OK) continue;  // does not fit: skip
+        for (int w = 1; w <= g.per_cu_max; ++w)
+            for (int o = 0; o <= (uneven ? 1 : 0); ++o) cand.push_back(hpc_tune{w, copies, o, 0});
+    }
+    if (cand.empty()) return fail(HPC_ERR_UNSUPPORTED, "hpc_plan_autotune: no configuration fits");
+    hipEvent_t e0, e1;
+    HPC_HIP(hipEventCreate(&e0));
+    HPC_HIP(hipEventCreate(&e1));
+    auto run = [&](const hpc_tune& t, float* ms) -> int {
+        ResGeo g;
+        int r = plan_geometry(plan, t, &g);
+        if (r) return r;
+        HPC_HIP(hipMemcpyAsync(plan->tC, C, (size_t)plan->c_len * 4, hipMemcpyDeviceToDevice, st));
+        const hpc::LloydArgs a = plan_args(plan, X, m, idx, plan->tC, max_iter, 0.0, plan->tf,
+                                           plan->tit, nullptr, t.order);
+        HPC_HIP(hipEventRecord(e0, st));
+        r = plan_launch(plan, a, g, st);
+        if (r) return r;
+        HPC_HIP(hipEventRecord(e1, st));
+        HPC_HIP(hipEventSynchronize(e1));
+        HPC_HIP(hipEventElapsedTime(ms, e0, e1));
+        return HPC_OK;
+    };
+    float warm = 0.f;
+    rc = run(cand[0], &warm);
+    double tbest = 1e300;
+    hpc_tune tb = cand[0];
+    for (size_t i = 0; rc == HPC_OK && i < cand.size(); ++i) {
+        float a = 0.f, b = 0.f;
+        rc = run(cand[i], &a);
+        if (rc == HPC_OK) rc = run(cand[i], &b);
+        const double t = std::min(a, b);
+        if (rc == HPC_OK && t < tbest) {
+            tbest = t;
+            tb = cand[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = hpc_plan_set_tune(plan, &tb);
+    if (rc) return rc;
+    *best = tb;
+    if (best_ms) *best_ms = tbest;
+    return HPC_OK;
+}
+
+int hpc_plan_lloyd(hpc_plan plan, const float* X, int64_t m, const int64_t* idx, float* C,
+                   int32_t max_iter, double rel_tol, double* f_out, int32_t* iters_out,
+                   int32_t* labels_out, void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_lloyd");
+    if (rc) return rc;
+    rc = lloyd_opts_ok("hpc_plan_lloyd", X, m, idx, C, max_iter, rel_tol, f_out, iters_out);
+    if (rc) return rc;
+    const hpc::LloydArgs a = plan_args(plan, X, m, idx, C, max_iter, rel_tol, f_out, iters_out,
+                                       labels_out, plan->tune.order);
+    return plan_launch(plan, a, plan->geo, static_cast<hipStream_t>(hip_stream));
+}
+
+int hpc_plan_draw(hpc_plan plan, int64_t m, int64_t* idx, void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_draw");
+    if (rc) return rc;
+    if (m < 1 || !idx) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_draw: need m >= 1, idx");
+    plan_draw(plan, m, idx, static_cast<hipStream_t>(hip_stream));
+    HPC_HIP(hipGetLastError());
+    return HPC_OK;
+}
+
+int hpc_plan_advance(hpc_plan plan, uint64_t id_stride, void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_advance");
+    if (rc) return rc;
+    plan_advance(plan, id_stride, static_cast<hipStream_t>(hip_stream));
+    HPC_HIP(hipGetLastError());
+    return HPC_OK;
+}
+
+int hpc_plan_round(hpc_plan plan, const float* X, int64_t m, int64_t* idx, float* C, float* C_inc,
+                   double* f_inc, int32_t max_iter, double rel_tol, double* f_out,
+                   int32_t* iters_out, uint64_t id_stride, void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_round");
+    if (rc) return rc;
+    rc = lloyd_opts_ok("hpc_plan_round", X, m, idx, C, max_iter, rel_tol, f_out, iters_out);
+    if (rc) return rc;
+    if (!C_inc || !f_inc) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_round: NULL incumbents");
+    return plan_enqueue_round(plan, X, m, idx, C, C_inc, f_inc, max_iter, rel_tol, f_out,
+                              iters_out, id_stride, static_cast<hipStream_t>(hip_stream));
+}
+
+int hpc_plan_capture_round(hpc_plan plan, const float* X, int64_t m, int64_t* idx, float* C,
+                           float* C_inc, double* f_inc, int32_t max_iter, double rel_tol,
+                           double* f_out, int32_t* iters_out, uint64_t id_stride) {
+    int rc = plan_check(plan, "hpc_plan_capture_round");
+    if (rc) return rc;
+    rc = lloyd_opts_ok("hpc_plan_capture_round", X, m, idx, C, max_iter, rel_tol, f_out, iters_out);
+    if (rc) return rc;
+    if (!C_inc || !f_inc)
+        return fail(HPC_ERR_INVALID_ARG, "hpc_plan_capture_round: NULL incumbents");
+    if (!plan->cap) HPC_HIP(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking));
+    if (plan->exec) {
+        HPC_HIP(hipGraphExecDestroy(plan->exec));
+        plan->exec = nullptr;
+    }
+    HPC_HIP(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
+    rc = plan_enqueue_round(plan, X, m, idx, C, C_inc, f_inc, max_iter, rel_tol, f_out, iters_out,
+                            id_stride, plan->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(plan->cap, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ee != hipSuccess)
+        return fail(HPC_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+    const hipError_t ei = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        plan->exec = nullptr;
+        return fail(HPC_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    }
+    return HPC_OK;
+}
+
+int hpc_plan_replay(hpc_plan plan, int32_t n_rounds, void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_replay");
+    if (rc) return rc;
+    if (!plan->exec) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_replay: no captured round");
+    if (n_rounds < 0) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_replay: n_rounds < 0");
+    for (int32_t r = 0; r < n_rounds; ++r)
+        HPC_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(hip_stream)));
+    return HPC_OK;
+}
+
+int hpc_plan_reset_ids(hpc_plan plan, void* hip_stream) {
+    int rc = plan_check(plan, "hpc_plan_reset_ids");
+    if (rc) return rc;
+    HPC_HIP(hipMemcpyAsync(plan->desc_dev, plan->desc_init, (size_t)plan->n * sizeof(hpc_sample_desc),
+                           hipMemcpyDeviceToDevice, static_cast<hipStream_t>(hip_stream)));
+    return HPC_OK;
 }
 
 }  // extern "C"

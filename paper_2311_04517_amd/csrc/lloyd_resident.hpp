@@ -323,21 +323,19 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
             for (int e = tid; e < n_cand * D; e += NT)
                 L.crow[e] = (double)sv.row(L.ints[4 + e / D])[e % D];
             __syncthreads();
-            // one candidate at a time keeps a single FP64 row live
+            // the potentials of all candidates in one stream over the chunk
             double pt[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int b0 = lo; b0 < hi; b0 += 16) {
+                const int i = b0 + p;
+                float xq[DL];
+                load_pt(i, xq);
+                const double dd = i < hi ? d2[i] : 0.0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t >= n_cand) continue;
-                double acc_t = 0.0;
-                for (int b0 = lo; b0 < hi; b0 += 16) {
-                    const int i = b0 + p;
-                    float xq[DL];
-                    load_pt(i, xq);
-                    const double dd = i < hi ? d2[i] : 0.0;
+                for (int t = 0; t < 4; ++t) {
+                    if (t >= n_cand) continue;
                     const double v = quarter_dist64<D>(xq, L.crow + t * D);
-                    if (i < hi && g == 0) acc_t += v < dd ? v : dd;
+                    if (i < hi && g == 0) pt[t] += v < dd ? v : dd;
                 }
-                pt[t] = acc_t;
             }
             block_sum_n<NT, 4>(pt, L.red);
             int tb = 0;

@@ -96,3 +96,72 @@ def test_binding_refuses_cpu_tensors():
     X = torch.zeros(10, 4)
     with pytest.raises(TypeError):
         api.assign_sse(X, torch.zeros(2, 4))
+
+
+def test_plan_validation(L):
+    h = ct.c_void_p()
+    good = _desc((0, 0, 10, 3))
+    _err(L, L.hpc_plan_create(4, good, 1, 10, 12, 0, None))                  # NULL out
+    _err(L, L.hpc_plan_create(0, good, 1, 10, 12, 0, ct.byref(h)))           # d = 0
+    _err(L, L.hpc_plan_create(4, good, 1, 10, 12, 5, ct.byref(h)))           # precision
+    _err(L, L.hpc_plan_create(4, _desc((0, 0, 2, 3)), 1, 10, 12, 0, ct.byref(h)))   # s < k
+    _err(L, L.hpc_plan_create(4, _desc((5, 0, 10, 3)), 1, 10, 12, 0, ct.byref(h)))  # idx range
+    _err(L, L.hpc_plan_create(4, good, 0, 10, 12, 0, ct.byref(h)))           # no samples
+    assert h.value is None
+    t = _lib.Tune(0, 0, 0, 0)
+    _err(L, L.hpc_plan_set_tune(None, ct.byref(t)))
+    _err(L, L.hpc_plan_get_tune(None, ct.byref(t)))
+    _err(L, L.hpc_plan_replay(None, 1, None))
+    _err(L, L.hpc_plan_lloyd(None, P, 10, P, P, 3, 0.0, P, P, None, None))
+    _err(L, L.hpc_plan_round(None, P, 10, P, P, P, P, 3, 0.0, P, P, 0, None))
+    _err(L, L.hpc_plan_capture_round(None, P, 10, P, P, P, P, 3, 0.0, P, P, 0))
+    _err(L, L.hpc_plan_reset_ids(None, None))
+    buf = ct.create_string_buffer(8)
+    _err(L, L.hpc_plan_tune_key(None, buf, 8))
+    assert L.hpc_plan_destroy(None) == _lib.HPC_OK
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    from paper_2311_04517_amd import tuning
+
+    p = str(tmp_path / "sub" / "tune.json")
+    assert tuning.load(p) == {}
+    tuning.store({"gfx950|d32|p0|n2^10|k2^5|s2^14": {"wg_per_cu": 2, "copies": 4, "order": 0,
+                                                      "ms": 3.1}}, p)
+    db = tuning.load(p)
+    assert db["gfx950|d32|p0|n2^10|k2^5|s2^14"]["copies"] == 4
+
+    class FakePlan:
+        def tune_key(self):
+            return "gfx950|d32|p0|n2^10|k2^5|s2^14"
+
+        def set_tune(self, **cfg):
+            self.cfg = cfg
+
+    fp = FakePlan()
+    cfg, ms = tuning.tuned(fp, None, None, None, path=p)
+    assert ms is None and fp.cfg == {"wg_per_cu": 2, "copies": 4, "order": 0}
+
+
+def test_plan_draw_advance_validation(L):
+    _err(L, L.hpc_plan_draw(None, 10, P, None))
+    _err(L, L.hpc_plan_advance(None, 1, None))
+
+
+def test_setenc_validation(L):
+    h = ct.c_void_p()
+    _err(L, L.hpc_setenc_create(33, 25, 1024, 8, 0, ct.byref(h)))   # d > 32
+    _err(L, L.hpc_setenc_create(32, 65, 1024, 8, 0, ct.byref(h)))   # k > 64
+    _err(L, L.hpc_setenc_create(32, 25, 8, 8, 0, ct.byref(h)))      # n_enc < 16
+    _err(L, L.hpc_setenc_create(32, 25, 1024, 0, 0, ct.byref(h)))   # max_batch < 1
+    _err(L, L.hpc_setenc_create(32, 25, 1024, 8, 0, None))
+    assert h.value is None
+    n = ct.c_int64()
+    _err(L, L.hpc_setenc_param_count(None, ct.byref(n)))
+    _err(L, L.hpc_setenc_get_params(None, 0, P))
+    _err(L, L.hpc_setenc_propose(None, P, 10, P, 10, _desc((0, 0, 10, 3)), 1, P, 12, None))
+    _err(L, L.hpc_setenc_grad(None, P, 10, P, 10, _desc((0, 0, 10, 3)), 1, P, 12, None, None))
+    _err(L, L.hpc_setenc_adam(None, ct.c_float(1e-3), None))
+    _err(L, L.hpc_learned_seed(None, P, 10, P, 10, _desc((0, 0, 10, 3)), 1, P, P, 12, 0, P, P,
+                               None, None))
+    assert L.hpc_setenc_destroy(None) == _lib.HPC_OK
