@@ -313,11 +313,12 @@ int hpc_plan_reset_ids(hpc_plan plan, void *hip_stream);
  * Parameters are FP32 masters laid out flat in the order W1 (d x 256), b1,
  * W2 (256 x 256), b2, Wh (256 x k*d), bh, matrices row-major; the kernels
  * use the weights rounded to BF16 (matrix cores, FP32 accumulation).
- * Training minimises the symmetric nearest-neighbour (Chamfer) distance
- * between o and the target centroids T in normalised coordinates:
- *   L = mean over samples of (1/k) sum_j min_l |o_j - T~_l|^2
- *                          + (1/k) sum_l min_j |o_j - T~_l|^2,
- * T~ = (T - mu) / sigma, with Adam (lr given, betas 0.9 / 0.999, eps 1e-8).
+ * Training minimises, with Adam (lr given, betas 0.9 / 0.999, eps 1e-8),
+ * the distance between o (as k rows of d) and the target centroids in
+ * normalised coordinates T~ = (T - mu) / sigma after a greedy one-to-one
+ * pairing pi (k times, the closest still-unpaired proposal / target rows;
+ * ties to the lowest proposal, then target, index):
+ *   L = mean over samples of (1/k) sum_j |o_j - T~_pi(j)|^2.
  * A model is used from one stream at a time.
  * ------------------------------------------------------------------------ */
 typedef struct hpc_setenc_s *hpc_setenc;

@@ -20,13 +20,15 @@ of the K-means++ seeding on the same sample.  The model:
     proposal       P = mu + sigma * reshape(o, k, d)
 
 Training target: the centroids T the method converges to on the same
-sample (K-means++ then Lloyd), compared in normalised coordinates with the
-symmetric nearest-neighbour (Chamfer) loss, which does not depend on the
-order of the rows:
+sample (K-means++ then Lloyd), compared in normalised coordinates after a
+one-to-one greedy matching, which does not depend on the order of the rows:
+repeatedly pair the closest proposal row O_j and target row T~_l among the
+rows not yet paired (ties: lowest j, then lowest l), giving a permutation pi;
 
-    L(O, T~) = (1/k) sum_j min_l |O_j - T~_l|^2 + (1/k) sum_l min_j |O_j - T~_l|^2
+    L(O, T~) = (1/k) sum_j |O_j - T~_pi(j)|^2,
 
-(argmin ties: lowest index), averaged over the samples of a batch.
+averaged over the samples of a batch (pi is held fixed when
+differentiating).
 
 Every function is plain numpy in float64; the encoder's gradient is the
 chain rule written out layer by layer.
@@ -72,24 +74,37 @@ def propose(params, S, k: int):
     return mu + sigma * o.reshape(k, -1)
 
 
-def chamfer(O, Tn):
-    """Symmetric nearest-neighbour loss between O (k x d) and Tn (k' x d),
-    and its gradient with respect to O."""
+def greedy_match(O, Tn):
+    """The greedy one-to-one pairing pi (pi[j] = target of proposal j) of
+    two k x d row sets by squared distance."""
     O = np.asarray(O, dtype=np.float64)
     Tn = np.asarray(Tn, dtype=np.float64)
-    k, kt = O.shape[0], Tn.shape[0]
-    D = ((O[:, None, :] - Tn[None, :, :]) ** 2).sum(axis=2)  # k x k'
-    jl = D.argmin(axis=1)  # nearest target of each proposal
-    lj = D.argmin(axis=0)  # nearest proposal of each target
-    loss = D[np.arange(k), jl].sum() / k + D[lj, np.arange(kt)].sum() / kt
-    g = np.zeros_like(O)
-    g += 2.0 / k * (O - Tn[jl])
-    np.add.at(g, lj, 2.0 / kt * (O[lj] - Tn))
-    return loss, g
+    k = O.shape[0]
+    D = ((O[:, None, :] - Tn[None, :, :]) ** 2).sum(axis=2)
+    pi = np.full(k, -1)
+    free_j = np.ones(k, dtype=bool)
+    free_l = np.ones(k, dtype=bool)
+    for _ in range(k):
+        M = np.where(free_j[:, None] & free_l[None, :], D, np.inf)
+        j, l = np.unravel_index(np.argmin(M), M.shape)  # first minimum in row-major order
+        pi[j] = l
+        free_j[j] = False
+        free_l[l] = False
+    return pi
+
+
+def match_loss(O, Tn):
+    """Matching loss of one sample and its gradient with respect to O."""
+    O = np.asarray(O, dtype=np.float64)
+    Tn = np.asarray(Tn, dtype=np.float64)
+    k = O.shape[0]
+    pi = greedy_match(O, Tn)
+    E = O - Tn[pi]
+    return (E ** 2).sum() / k, 2.0 / k * E
 
 
 def loss_and_grads(params, sets, targets, k: int):
-    """Mean Chamfer loss over a batch of (point set, target centroids)
+    """Mean matching loss over a batch of (point set, target centroids)
     pairs and the gradient of every parameter."""
     B = len(sets)
     grads = {n: np.zeros_like(params[n]) for n in PARAM_NAMES}
@@ -98,7 +113,7 @@ def loss_and_grads(params, sets, targets, k: int):
         mu, sigma, St = normalise(S)
         c = encode(params, St)
         Tn = (np.asarray(T, dtype=np.float64) - mu) / sigma
-        loss, gO = chamfer(c["o"].reshape(k, -1), Tn)
+        loss, gO = match_loss(c["o"].reshape(k, -1), Tn)
         total += loss / B
         do = gO.ravel() / B
         grads["Wh"] += np.outer(c["p"], do)
@@ -117,19 +132,26 @@ def loss_and_grads(params, sets, targets, k: int):
 
 def min_kink_margin(params, sets, targets, k: int) -> float:
     """Smallest distance of any ReLU pre-activation from 0 and of any
-    Chamfer argmin from a tie over the batch: where both are large, the
-    loss is smooth around params and central differences are meaningful."""
+    greedy-matching choice from a tie over the batch: where both are large,
+    the loss is smooth around params and central differences are
+    meaningful."""
     m = np.inf
     for S, T in zip(sets, targets):
         mu, sigma, St = normalise(S)
         c = encode(params, St)
         m = min(m, np.abs(c["z1"]).min(), np.abs(c["z2"]).min())
         Tn = (np.asarray(T, dtype=np.float64) - mu) / sigma
-        D = ((c["o"].reshape(k, -1)[:, None, :] - Tn[None]) ** 2).sum(axis=2)
-        for A in (D, D.T):
-            s = np.sort(A, axis=1)
-            if s.shape[1] > 1:
-                m = min(m, (s[:, 1] - s[:, 0]).min())
+        O = c["o"].reshape(k, -1)
+        D = ((O[:, None, :] - Tn[None]) ** 2).sum(axis=2)
+        pi = greedy_match(O, Tn)
+        free_j = np.ones(k, dtype=bool)
+        free_l = np.ones(k, dtype=bool)
+        for j in np.argsort(D[np.arange(k), pi], kind="stable"):
+            M = np.where(free_j[:, None] & free_l[None, :], D, np.inf)
+            M[j, pi[j]] = np.inf
+            m = min(m, M.min() - D[j, pi[j]])
+            free_j[j] = False
+            free_l[pi[j]] = False
     return float(m)
 
 

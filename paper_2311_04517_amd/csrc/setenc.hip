@@ -166,7 +166,7 @@ enc::RowArgs row_args(hpc_setenc s, const float* X, int64_t m, const int64_t* id
 // already on the device).  C nullable.
 int forward(hpc_setenc s, const float* X, int64_t m, const int64_t* idx, int32_t n, float* C,
             hipStream_t st) {
-    hipLaunchKernelGGL(enc::k_enc_stats, dim3(n), dim3(enc::NT), 0, st, X, s->d, idx,
+    hipLaunchKernelGGL(enc::k_enc_stats, dim3(n), dim3(enc::NT), 0, st, X, m, s->d, idx,
                        (const hpc_sample_desc*)s->desc_dev, s->n_enc, s->stats);
     const enc::RowArgs a = row_args(s, X, m, idx);
     hipLaunchKernelGGL(enc::k_enc_rows<false>, dim3(s->chunks, n), dim3(enc::NT), 0, st, a);

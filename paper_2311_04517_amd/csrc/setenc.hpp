@@ -92,8 +92,14 @@ __device__ __forceinline__ int n_points(const hpc_sample_desc& ds, int n_enc) {
 // n_b = min(s, n_enc) points of the sample), sigma = sqrt(mean |x - mu|^2)
 // (1 if zero).  FP64 sums.  One workgroup per sample.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_enc_stats(const float* __restrict__ X, int32_t d,
-                                                  const int64_t* __restrict__ idx,
+// An index outside [0, m) reads as a row of zeros (as in the Lloyd gather).
+__device__ __forceinline__ float enc_coord(const float* __restrict__ X, int64_t m, int32_t d,
+                                          int64_t row, int q) {
+    return (row >= 0 && row < m) ? X[row * d + q] : 0.f;
+}
+
+__global__ __launch_bounds__(NT) void k_enc_stats(const float* __restrict__ X, int64_t m,
+                                                  int32_t d, const int64_t* __restrict__ idx,
                                                   const hpc_sample_desc* __restrict__ desc,
                                                   int32_t n_enc, float* __restrict__ stats) {
     __shared__ double red[NT / kWave];
@@ -102,16 +108,17 @@ __global__ __launch_bounds__(NT) void k_enc_stats(const float* __restrict__ X, i
     const int n = n_points(ds, n_enc);
     for (int q = 0; q < d; ++q) {
         double a = 0.0;
-        for (int i = threadIdx.x; i < n; i += NT) a += (double)X[idx[ds.idx_offset + i] * d + q];
+        for (int i = threadIdx.x; i < n; i += NT)
+            a += (double)enc_coord(X, m, d, idx[ds.idx_offset + i], q);
         a = block_sum<NT>(a, red);
         if (threadIdx.x == 0) mu[q] = a / n;
     }
     __syncthreads();
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += NT) {
-        const float* x = X + idx[ds.idx_offset + i] * d;
+        const int64_t row = idx[ds.idx_offset + i];
         for (int q = 0; q < d; ++q) {
-            const double e = (double)x[q] - mu[q];
+            const double e = (double)enc_coord(X, m, d, row, q) - mu[q];
             v = __fma_rn(e, e, v);
         }
     }
@@ -199,11 +206,12 @@ __global__ __launch_bounds__(NT) void k_enc_rows(RowArgs a) {
         // B operand of layer 1: dims 8g..8g+7 of this lane's point
         bf16x8 xop;
         {
-            const float* x = valid ? a.X + a.idx[ds.idx_offset + p] * a.d : nullptr;
+            const int64_t xr = valid ? a.idx[ds.idx_offset + p] : -1;
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
                 const int q = 8 * g + v;
-                const float xv = (valid && q < a.d) ? (x[q] - st[q]) * inv_sigma : 0.f;
+                const float xv =
+                    (valid && q < a.d) ? (enc_coord(a.X, a.m, a.d, xr, q) - st[q]) * inv_sigma : 0.f;
                 xop[v] = (__bf16)xv;
             }
         }
@@ -340,9 +348,12 @@ __global__ void k_enc_head(const float* __restrict__ pooled, const float* __rest
     }
 }
 
-// Chamfer loss of a sample in normalised coordinates (FP64; argmin ties to
-// the lowest index) and its gradient dL/do / B.  One workgroup per sample;
-// k <= 64.  loss_part[b] = the sample's loss / B.
+// Matching loss of a sample in normalised coordinates and its gradient
+// dL/do / B.  The pairing is greedy and one-to-one: k times, the closest
+// (proposal j, target l) pair among the rows not yet paired is taken (FP64
+// squared distances; ties to the lowest j, then the lowest l).  Loss
+// (1/k) sum_j |o_j - T~_pi(j)|^2.  One workgroup of 256 per sample; k <= 64.
+// loss_part[b] = the sample's loss / B.
 __global__ __launch_bounds__(256) void k_enc_loss(const float* __restrict__ obuf,
                                                   const float* __restrict__ T,
                                                   const float* __restrict__ stats,
@@ -350,16 +361,18 @@ __global__ __launch_bounds__(256) void k_enc_loss(const float* __restrict__ obuf
                                                   int32_t k, int32_t d, int32_t B,
                                                   float* __restrict__ dout,
                                                   double* __restrict__ loss_part) {
-    __shared__ double Dm[64][65];
-    __shared__ int jl[64], lj[64];
-    __shared__ double red[4];
-    const int b = blockIdx.x;
+    __shared__ double Dm[64 * 64];
+    __shared__ int pi[64];
+    __shared__ unsigned char free_j[64], free_l[64];
+    __shared__ double wv[4];
+    __shared__ int wi[4];
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const hpc_sample_desc ds = desc[b];
     const float* st = stats + (size_t)b * (DIN + 2);
     const float* o = obuf + (size_t)b * k * d;
     const float* t = T + ds.c_offset;
     const double inv = 1.0 / (double)st[DIN];
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    for (int e = tid; e < k * k; e += blockDim.x) {
         const int j = e / k, l = e % k;
         double s = 0.0;
         for (int q = 0; q < d; ++q) {
@@ -367,34 +380,56 @@ __global__ __launch_bounds__(256) void k_enc_loss(const float* __restrict__ obuf
             const double df = (double)o[j * d + q] - tn;
             s = __fma_rn(df, df, s);
         }
-        Dm[j][l] = s;
+        Dm[e] = s;
+    }
+    if (tid < 64) {
+        free_j[tid] = 1;
+        free_l[tid] = 1;
     }
     __syncthreads();
-    double acc = 0.0;
-    if (threadIdx.x < k) {
-        const int j = threadIdx.x;
-        int bl = 0;
-        for (int l = 1; l < k; ++l)
-            if (Dm[j][l] < Dm[j][bl]) bl = l;
-        jl[j] = bl;
-        acc += Dm[j][bl];
-    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + k) {
-        const int l = threadIdx.x - 64;
-        int bj = 0;
-        for (int j = 1; j < k; ++j)
-            if (Dm[j][l] < Dm[bj][l]) bj = j;
-        lj[l] = bj;
-        acc += Dm[bj][l];
+    for (int step = 0; step < k; ++step) {
+        double v = __builtin_huge_val();
+        int ix = 0x7fffffff;
+        for (int e = tid; e < k * k; e += blockDim.x)
+            if (free_j[e / k] && free_l[e % k] && (Dm[e] < v || (Dm[e] == v && e < ix))) {
+                v = Dm[e];
+                ix = e;
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, 64);
+            const int oi = __shfl_xor(ix, off, 64);
+            if (ov < v || (ov == v && oi < ix)) {
+                v = ov;
+                ix = oi;
+            }
+        }
+        if (lane == 0) {
+            wv[w] = v;
+            wi[w] = ix;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double bv = wv[0];
+            int bi = wi[0];
+            for (int q = 1; q < 4; ++q)
+                if (wv[q] < bv || (wv[q] == bv && wi[q] < bi)) {
+                    bv = wv[q];
+                    bi = wi[q];
+                }
+            pi[bi / k] = bi % k;
+            free_j[bi / k] = 0;
+            free_l[bi % k] = 0;
+        }
+        __syncthreads();
     }
-    acc = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) loss_part[b] = acc / k / B;
-    for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
+    double acc = tid < k ? Dm[tid * k + pi[tid]] : 0.0;
+    acc = block_sum<256>(acc, wv);
+    if (tid == 0) loss_part[b] = acc / k / B;
+    for (int e = tid; e < k * d; e += blockDim.x) {
         const int j = e / d, q = e % d;
-        const double oj = (double)o[e];
-        double gsum = oj - ((double)t[jl[j] * d + q] - (double)st[q]) * inv;
-        for (int l = 0; l < k; ++l)
-            if (lj[l] == j) gsum += oj - ((double)t[l * d + q] - (double)st[q]) * inv;
-        dout[(size_t)b * k * d + e] = (float)(2.0 * gsum / k / B);
+        const double tn = ((double)t[pi[j] * d + q] - (double)st[q]) * inv;
+        dout[(size_t)b * k * d + e] = (float)(2.0 * ((double)o[e] - tn) / k / B);
     }
 }
 

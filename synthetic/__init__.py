@@ -137,3 +137,34 @@ def uneven_sizes(n: int, *, seed: int = 3, s_range=(1_000, 100_000), k_range=(2,
     s = rng.integers(s_range[0], s_range[1] + 1, size=n)
     k = rng.integers(k_range[0], k_range[1] + 1, size=n)
     return s.astype(np.int64), k.astype(np.int64)
+
+
+def mixture_family(n_sets: int, s: int, *, d: int = 32, n_comp: int = 25, seed: int,
+                   template: bool = False, template_seed: int = 0, device="cpu"):
+    """n_sets independent point sets of s points, set i occupying rows
+    [i*s, (i+1)*s) of the returned X (n_sets*s x d, float32).
+
+    Each set is drawn from its own n_comp-component mixture with equal
+    weights and diagonal std U[0.5, 3] per component and dimension.  With
+    ``template`` False the centres of every set are fresh, U[-20, 20]^d (the
+    learned initializer's training family).  With ``template`` True they
+    are a shared random configuration T0 ~ U[-20, 20]^d (drawn from
+    ``template_seed``, the same for every call), scaled by a ~
+    U[0.5, 2], shifted by t ~ U[-20, 20]^d and jittered by N(0, 0.5^2) per
+    coordinate: a family whose normalised structure repeats.
+    Returns (X, centres as n_sets x n_comp x d float32)."""
+    g = _gen(seed, device)
+    kw = dict(generator=g, device=device, dtype=torch.float32)
+    if template:
+        gt = _gen(104729 + template_seed, device)
+        T0 = (torch.rand(n_comp, d, generator=gt, device=device) * 2 - 1) * 20.0
+        a = 0.5 + 1.5 * torch.rand(n_sets, 1, 1, **kw)
+        t = (torch.rand(n_sets, 1, d, **kw) * 2 - 1) * 20.0
+        cen = T0.unsqueeze(0) * a + t + 0.5 * torch.randn(n_sets, n_comp, d, **kw)
+    else:
+        cen = (torch.rand(n_sets, n_comp, d, **kw) * 2 - 1) * 20.0
+    sig = 0.5 + 2.5 * torch.rand(n_sets, n_comp, d, **kw)
+    lab = torch.randint(0, n_comp, (n_sets, s), generator=g, device=device)
+    sets = torch.arange(n_sets, device=device).unsqueeze(1).expand(n_sets, s)
+    X = cen[sets, lab] + sig[sets, lab] * torch.randn(n_sets, s, d, **kw)
+    return X.reshape(n_sets * s, d).contiguous(), cen

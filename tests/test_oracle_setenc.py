@@ -1,9 +1,7 @@
 """Pins of the FP64 set-encoder oracle (learned initializer): a forward pass
-worked by hand, the linear regime's closed form, the Chamfer loss's
-defining properties checked against explicit loops, and every gradient
+worked by hand, the linear regime's closed form, the matching
+loss's defining properties, and every gradient
 entry against central finite differences of the oracle's own loss."""
-import itertools
-
 import numpy as np
 import pytest
 
@@ -44,31 +42,39 @@ def test_linear_regime_closed_form():
     assert np.allclose(St.mean(0), 0, atol=1e-14) and np.isclose((St ** 2).sum(1).mean(), 1.0)
 
 
-def _chamfer_loops(O, T):
-    k, kt = len(O), len(T)
-    t1 = 0.0
-    for j in range(k):
-        t1 += min(sum((O[j][q] - T[l][q]) ** 2 for q in range(O.shape[1])) for l in range(kt))
-    t2 = 0.0
-    for l in range(kt):
-        t2 += min(sum((O[j][q] - T[l][q]) ** 2 for q in range(O.shape[1])) for j in range(k))
-    return t1 / k + t2 / kt
-
-
-def test_chamfer_properties():
+def test_greedy_matching_properties():
     rng = np.random.default_rng(1)
-    T = rng.normal(size=(4, 3))
-    loss, g = setenc.chamfer(T, T)
+    k, d = 6, 3
+    T = rng.normal(size=(k, d))
+    loss, g = setenc.match_loss(T, T)
     assert loss == 0.0 and not g.any()
-    O = rng.normal(size=(4, 3))
-    loss, g = setenc.chamfer(O, T)
-    assert np.isclose(loss, _chamfer_loops(O, T), rtol=1e-14)
-    for perm in itertools.permutations(range(4)):
-        assert np.isclose(setenc.chamfer(O[list(perm)], T)[0], loss, rtol=1e-14)
-        assert np.isclose(setenc.chamfer(O, T[list(perm)])[0], loss, rtol=1e-14)
-    # one centre: twice the squared distance
-    l1, g1 = setenc.chamfer(O[:1], T[:1])
-    assert np.isclose(l1, 2 * ((O[0] - T[0]) ** 2).sum()) and np.allclose(g1, 4 * (O[:1] - T[:1]))
+    # a shuffled, slightly perturbed copy is matched back to its origin
+    perm = rng.permutation(k)
+    O = T[perm] + rng.normal(size=(k, d)) * 1e-3
+    assert np.array_equal(T[setenc.greedy_match(O, T)], T[perm])
+    # on random rows: a permutation, each pair the closest among the rows
+    # still free when it was taken (pairs taken in increasing distance)
+    O = rng.normal(size=(k, d))
+    pi = setenc.greedy_match(O, T)
+    assert sorted(pi) == list(range(k))
+    D = ((O[:, None, :] - T[None]) ** 2).sum(axis=2)
+    used_j, used_l = set(), set()
+    for j in np.argsort(D[np.arange(k), pi], kind="stable"):
+        for jj in range(k):
+            for ll in range(k):
+                if jj not in used_j and ll not in used_l:
+                    assert D[j, pi[j]] <= D[jj, ll]
+        used_j.add(j)
+        used_l.add(pi[j])
+    loss, g = setenc.match_loss(O, T)
+    assert np.isclose(loss, sum(((O[j] - T[pi[j]]) ** 2).sum() for j in range(k)) / k)
+    # relabelling proposals or targets relabels the pairing, not the loss
+    q = rng.permutation(k)
+    assert np.isclose(setenc.match_loss(O[q], T)[0], loss, rtol=1e-14)
+    assert np.isclose(setenc.match_loss(O, T[q])[0], loss, rtol=1e-14)
+    # one centre: the squared distance
+    l1, g1 = setenc.match_loss(O[:1], T[:1])
+    assert np.isclose(l1, ((O[0] - T[0]) ** 2).sum()) and np.allclose(g1, 2 * (O[:1] - T[:1]))
 
 
 def _batch(rng, d, k, B=2, n=7):
