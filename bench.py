@@ -42,6 +42,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="MFMA type of the distance screening (decisions are FP64-exact)")
+    ap.add_argument("--no-tts", dest="tts", action="store_false",
+                    help="skip the time-to-SSE comparison")
+    ap.add_argument("--tts-samples", type=int, default=64,
+                    help="samples of the single-worker reference run (the oracle's f_ref)")
+    ap.add_argument("--tts-rounds", type=int, default=4, help="rounds of each batched form")
+    ap.add_argument("--train-pairs", type=int, default=50_000,
+                    help="training pairs of the learned initializer (0: skip the learned form)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the default launch configuration instead of autotuning")
     ap.add_argument("--pmc-target", action="store_true",
@@ -164,6 +171,11 @@ def main():
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(X, C_before, r_first_timed, args, m, d, W, s, k)
+    tts = None
+    if args.tts:
+        plan.close()
+        f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
+        tts = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
 
     out = {
         "metric": "sample-point-iters/sec (k=25,d=32)",
@@ -189,6 +201,7 @@ def main():
         "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,
                        "frac": assign_gbs / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
+        "time_to_sse": tts,
     }
     print(json.dumps(out), flush=True)
 
@@ -217,6 +230,136 @@ def pmc_target(api, X, m, d, W, s, k, prec, seed):
     print("[bench] pmc target done", file=sys.stderr, flush=True)
 
 
+def _first_reach(api, X, hist, times, target, precision):
+    """Index and time of the first recorded incumbent whose full-data SSE is
+    within the target (SSE evaluated after the run, not timed)."""
+    for i in range(len(times)):
+        _, _, sse = api.assign_sse(X, hist[i], want_labels=False, want_counts=False,
+                                   precision=precision)
+        v = sse.item()
+        if v <= target:
+            return i, times[i], v
+    return None, None, v
+
+
+def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
+    """Time until the incumbent's full-data SSE is within 1e-3 of the
+    reference f_ref, for the plain single-worker form on the GPU and for
+    batched forms (W workers per round: FP32, BF16 screening, BF16 plus the
+    learned initializer on the cold round).  Each form records an HIP event
+    and a copy of its incumbent after every incumbent update; SSEs are
+    evaluated afterwards."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2311_04517_amd import learned
+
+    dev = X.device
+    stream = torch.cuda.current_stream()
+    N = args.tts_samples
+    res = {"threshold_rel": 1e-3, "workers": W, "rounds": args.tts_rounds}
+    # plain FP32 per sample (Algorithm 3 with one worker, sample after sample)
+    C_w = torch.full((k, d), float("nan"), device=dev)
+    f_hat = torch.full((1,), float("inf"), dtype=torch.float64, device=dev)
+    C = torch.empty_like(C_w)
+    idx = torch.empty(s, dtype=torch.int64, device=dev)
+    f1 = torch.empty(1, dtype=torch.float64, device=dev)
+    i1 = torch.empty(1, dtype=torch.int32, device=dev)
+    hist = torch.empty((N, k, d), device=dev)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(N + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for t in range(N):
+        api.draw_sample(m, s, args.seed, t, out=idx)
+        C.copy_(C_w)
+        desc, _, _ = api.make_desc([s], [k], seed=args.seed, sample_id=[t], d=d)
+        api.lloyd_batch(X, idx, desc, C, f_out=f1, iters_out=i1)
+        api.keep_best(C, f1, C_w, f_hat, k, d)
+        hist[t].copy_(C_w)
+        evs[t + 1].record(stream)
+    torch.cuda.synchronize()
+    t_plain = [evs[0].elapsed_time(e) for e in evs[1:]]
+    if f_ref is None:  # no oracle run: the plain form's own end point
+        _, _, sse = api.assign_sse(X, hist[N - 1], want_labels=False, want_counts=False)
+        f_ref = sse.item()
+        res["f_ref_source"] = "plain GPU form after all samples (no oracle run)"
+    else:
+        res["f_ref_source"] = "oracle"
+    res["f_ref"] = f_ref
+    target = f_ref * (1 + 1e-3)
+    i, t, v = _first_reach(api, X, hist, t_plain, target, api.PREC_FP32)
+    res["plain_fp32_per_sample"] = {"ms": t, "samples": None if i is None else i + 1,
+                                    "sse": v, "ms_all": t_plain[-1]}
+
+    model = None
+    if args.train_pairs > 0:
+        # the learned initializer, trained on method-generated pairs of the
+        # same family of mixtures (fresh 25-component mixtures in d = 32)
+        t0 = time.perf_counter()
+        model = api.SetEncoder(d, k, n_enc=1024, max_batch=32, seed=args.seed)
+        pool = 1024
+        n_pools = max(1, args.train_pairs // pool)
+        for q in range(n_pools):
+            Xp, _ = synthetic.mixture_family(pool, s, d=d, n_comp=k, seed=100_000 + q, device=dev)
+            desc_p, idx_len_p, c_len_p = api.make_desc([s] * pool, [k] * pool, seed=q,
+                                                       sample_id=range(pool), d=d)
+            idx_p = torch.arange(pool * s, dtype=torch.int64, device=dev)
+            T, _, _ = learned.method_targets(Xp, idx_p, desc_p, c_len_p)
+            learned.train(model, Xp, idx_p, desc_p, T, steps=pool // 32, batch=32,
+                          lr=2e-3 * 0.9 ** q, seed=q)
+            del Xp, idx_p, T
+        torch.cuda.synchronize()
+        res["learned_training"] = {"pairs": n_pools * pool, "seconds": time.perf_counter() - t0}
+
+    forms = [("batched_fp32", api.PREC_FP32, False), ("batched_bf16", api.PREC_BF16_MFMA, False)]
+    if model is not None:
+        forms.append(("batched_bf16_learned", api.PREC_BF16_MFMA, True))
+    for name, prec, use_learned in forms:
+        R = args.tts_rounds
+        desc, idx_len, c_len = api.make_desc([s] * W, [k] * W, seed=args.seed,
+                                             sample_id=range(W), d=d)
+        plan = api.Plan(d, desc, idx_len, c_len, precision=prec)
+        C_inc = torch.full((c_len,), float("nan"), device=dev)
+        f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device=dev)
+        Cr = torch.empty(c_len, device=dev)
+        Ck = torch.empty(c_len, device=dev)
+        idx = torch.empty(idx_len, dtype=torch.int64, device=dev)
+        f = torch.empty(W, dtype=torch.float64, device=dev)
+        it = torch.empty(W, dtype=torch.int32, device=dev)
+        hist = torch.empty((R, k, d), device=dev)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
+        acc = None
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        for r in range(R):
+            if r == 0 and use_learned:
+                plan.draw(m, idx)
+                _, _, _, _, acc = model.learned_seed(X, idx, desc, Cr, precision=prec, C_kpp=Ck)
+                plan.lloyd(X, idx, Cr, f_out=f, iters_out=it)
+                api.keep_best(Cr, f, C_inc, f_inc, k, d)
+                plan.advance(W)
+            else:
+                plan.round(X, idx, Cr, C_inc, f_inc, f, it)
+            Cb, _, _ = api.select_best(C_inc, f_inc, k, d)
+            hist[r].copy_(Cb)
+            evs[r + 1].record(stream)
+        torch.cuda.synchronize()
+        times = [evs[0].elapsed_time(e) for e in evs[1:]]
+        i, t, v = _first_reach(api, X, hist, times, target, prec)
+        res[name] = {"ms": t, "rounds": None if i is None else i + 1, "sse": v,
+                     "ms_per_round": [round(x, 3) for x in np.diff([0.0] + times)]}
+        if acc is not None:
+            res[name]["accepted_frac"] = acc.float().mean().item()
+        plan.close()
+    best = res.get("batched_bf16_learned") or res["batched_bf16"]
+    p = res["plain_fp32_per_sample"]["ms"]
+    res["speedup_vs_plain"] = (p / best["ms"]) if (p and best["ms"]) else None
+    if model is not None:
+        model.close()
+    return res
+
+
 def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
     """The FP64 oracle on a bounded sample of the same workload: the first
     samples of the first timed round, from the same incumbents, on the
@@ -242,10 +385,21 @@ def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
         done_spi += int(o["iters"].sum()) * s
         done_n += per
     del api
-    return {"value": done_spi / done_t, "unit": "sample-point-iters/s", "cores": n_threads,
-            "kind": "oracle",
-            "sample": f"{done_n} of the {W} samples of one round (same inputs and incumbents), "
-                      f"{done_t:.1f}s of CPU work on {n_threads} threads"}
+    out = {"value": done_spi / done_t, "unit": "sample-point-iters/s", "cores": n_threads,
+           "kind": "oracle",
+           "sample": f"{done_n} of the {W} samples of one round (same inputs and incumbents), "
+                     f"{done_t:.1f}s of CPU work on {n_threads} threads"}
+    if args.tts:
+        # the time-to-SSE threshold: the single-worker method (one worker,
+        # keep-the-best over N samples, then the full assignment), FP64
+        t0 = time.perf_counter()
+        wo = oracle.worker_loop(Xn, s=s, k=k, n_samples=args.tts_samples, seed=args.seed,
+                                want_labels=False)
+        out["time_to_sse_reference"] = {
+            "f_ref": wo["sse"], "samples": args.tts_samples, "seconds": time.perf_counter() - t0,
+            "cores": 1, "what": "oracle single-worker loop over the samples plus the full "
+                                "assignment (wall time, one thread)"}
+    return out
 
 
 if __name__ == "__main__":
