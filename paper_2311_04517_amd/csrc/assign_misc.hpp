@@ -112,6 +112,9 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
     screen_coeffs<PREC>(d, &alpha, &beta);
     const double cmax = red[NW];
     const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
+    unsigned kmask;
+    float qscale;
+    key_params(nblk, &kmask, &qscale);
     double fl = 0.0;
     const int64_t n_tiles = (m + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * NW + wid; tile < n_tiles;
@@ -128,11 +131,13 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
                 xq[t] = (valid && dim < d) ? X[i * d + dim] : 0.f;
             }
         }
-        const Top2 t2 = screen_tile<D, PREC>(xq, aop, nrm, nblk);
-        const float xn = cert_norm(point_norm2<D>(xq));
-        const bool ok = certified(t2, xn, ea, eb) || !valid;
-        int am = redecide64<D>(xq, !ok, top2_suffices(t2, xn, ea, eb), t2.a1 < k ? t2.a1 : 0,
-                               t2.a2 < k ? t2.a2 : 0, C64, k);
+        const float xn2 = point_norm2<D>(xq);
+        const Top3 t3 = screen_tile<D, PREC>(xq, aop, nrm, nblk, xn2, kmask);
+        const float xn = cert_norm(xn2);
+        const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
+        const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
+        int am = redecide64<D>(xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb),
+                               a1 < k ? a1 : 0, a2 < k ? a2 : 0, C64, k);
         if (valid) {
             // this lane's share of the objective: FP64 distance to the choice
             fl += n_valid > 0 ? quarter_part64<D>(xq, C64 + am * CS) : __builtin_huge_val();

@@ -386,8 +386,11 @@ __device__ __forceinline__ double centroid_max_norm(Smem<D, NT, PREC>& L, int k,
     return sqrt(mx);
 }
 
+// Up to d = 32 the kernel is held to 128 VGPRs (four waves per SIMD): the
+// tile loop then runs at twice the occupancy, at the price of a few
+// spilled values in the seeding and gather paths.
 template <int D, int NT, int PREC>
-__global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
+__global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArgs a) {
     extern __shared__ __align__(16) char smem[];
     using S = Smem<D, NT, PREC>;
     constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
@@ -466,6 +469,9 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
             double f_prev = __builtin_huge_val(), f = 0.0;
             int it = 0;
             const int copies = a.n_copies;
+            unsigned kmask;
+            float qscale;
+            key_params(nblk, &kmask, &qscale);
             for (;;) {
                 kmeanspp_wg<D, NT, PREC>(sv, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
                                          (uint64_t)it, nullptr, L);
@@ -493,11 +499,14 @@ __global__ __launch_bounds__(NT) void k_lloyd_resident(LloydArgs a) {
                 auto process = [&](int tile, const float (&xq)[DL]) {
                     const int i = tile * 16 + pl;
                     const bool valid = i < s;
-                    const Top2 t2 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk);
-                    const float xn = cert_norm(point_norm2<D>(xq));
-                    const bool ok = certified(t2, xn, ea, eb) || !valid;
-                    const int am = redecide64<D>(xq, !ok, top2_suffices(t2, xn, ea, eb), t2.a1,
-                                                 t2.a2, L.C64, k);
+                    const float xn2 = point_norm2<D>(xq);
+                    const Top3 t3 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk, xn2, kmask);
+                    const float xn = cert_norm(xn2);
+                    const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
+                    const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
+                    const int am = redecide64<D>(
+                        xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb), a1,
+                        a2 < k ? a2 : a1, L.C64, k);
                     if (valid) {
                         // this lane's share of the objective and of the sums
                         const double* cr = L.C64 + am * CS + g * DL;

@@ -14,18 +14,34 @@
 // the tile and dims [g*DL, (g+1)*DL) of that point (DL = D/4; the dims are
 // permuted consistently in A and B, which leaves the contraction
 // unchanged), and gets the scores of centroids 4g..4g+3 of each block.  The
-// four lanes of a point merge their best/runner-up with two XOR shuffles.
+// four lanes of a point merge their three best with two XOR exchanges.
 //
-// Certificate: let E(x) bound |s~_j - s_j| for the screened score; when
-// the screened gap s~_2 - s~_1 exceeds 2E the screened winner is the exact
-// argmin.  E(x) = alpha |x| cmax + beta cmax^2 with (u = 2^-24, u_b = 2^-8
-// plus the FP32-to-BF16 double rounding)
+// Keys.  Each screened score becomes the distance estimate v_j = fl(s~_j +
+// |x|~^2) (|x|~^2 the FP32 norm of the point, the same for every j),
+// clamped at +0, and its NB low mantissa bits are replaced by j
+// (2^NB >= padded k).  For non-negative floats the bit patterns order like
+// the values, so the three smallest keys -- found with integer min/max
+// only -- are the three smallest quantised estimates with their indices.
+// Padding rows (score +inf) give keys at or above 0x7F800000, above every
+// finite key.
+//
+// Certificate.  Let E(x) bound |s~_j - s_j| for the screened score, s_j the
+// exact score of the FP64 centroid; E(x) = alpha |x| cmax + beta cmax^2 with
+// (u = 2^-24, u_b = 2^-8 plus the FP32-to-BF16 double rounding)
 //   FP32 : alpha = (4d + 10) u          beta = (2d + 6) u
 //   BF16 : alpha = 4 u_b + 2 u_b^2 + (4d + 10) u (1 + u_b)^2   beta as FP32
 // i.e. the rounding of the operands to the MFMA input type, plus twice the
 // classical accumulation bound of d + 1 FP32 additions (the factor two
 // leaves room for the matrix unit's internal summation order), plus the
-// rounding of |c|^2 to FP32.  The test below uses 2.5 E.
+// rounding of |c|^2 to FP32.  The quantised key value q_j satisfies
+// q_j <= max(v_j, 0) < q_j (1 + 2^(NB-23)) + 0, and fl() adds a relative
+// 2^-24; the common error of |x|~^2 cancels between j.  Hence with q_1 <=
+// q_2 the two best keys, every j other than the winner has s_j > s_winner
+// whenever  q_2 - q_1 > 2E + 2^(NB-22) q_1 + 2^-23 (q_1 + q_2),  and the
+// test below uses the stronger  q_2 - q_1 > 2.5 E + 2^(NB-20) q_2  (the
+// left side grows faster in q_j than the right, so the runner-up is the
+// binding case).  The same test on the third key shows the exact argmin is
+// one of the two best.
 #pragma once
 
 #include "common.hpp"
@@ -127,54 +143,66 @@ __device__ __forceinline__ void load_quarter(const float* __restrict__ row, int 
     }
 }
 
-// Best, runner-up and third screened scores of a point (a1, a2: indices of
-// the best two).
-struct Top2 {
-    float b1, b2, b3;
-    int a1, a2;
+// The three smallest screening keys of a point, ascending.
+struct Top3 {
+    unsigned t1, t2, t3;
 };
 
-__device__ __forceinline__ void top2_push(Top2& t, float v, int j) {
-    const bool lt1 = v < t.b1, lt2 = v < t.b2, lt3 = v < t.b3;
-    t.b3 = lt2 ? t.b2 : (lt3 ? v : t.b3);
-    t.b2 = lt1 ? t.b1 : (lt2 ? v : t.b2);
-    t.a2 = lt1 ? t.a1 : (lt2 ? j : t.a2);
-    t.a1 = lt1 ? j : t.a1;
-    t.b1 = lt1 ? v : t.b1;
+// Key of centroid j: max(v, +0) with the low bits under `kmask` set to j.
+__device__ __forceinline__ unsigned screen_key(float v, unsigned kmask, unsigned j) {
+    const int bits = __float_as_int(v);
+    const unsigned pos = (unsigned)(bits > 0 ? bits : 0);  // negatives and -0 to +0
+    return (pos & ~kmask) | j;
+}
+
+// Insert a key into the ascending triple (compare-exchange chain).
+__device__ __forceinline__ void top3_insert(Top3& t, unsigned key) {
+    const unsigned c1 = max(t.t1, key);
+    t.t1 = min(t.t1, key);
+    const unsigned c2 = max(t.t2, c1);
+    t.t2 = min(t.t2, c1);
+    t.t3 = min(t.t3, c2);
 }
 
 // Merge with the lane at XOR distance o (the lanes hold disjoint centroid
-// sets).  Symmetric, ties to the lower index, so all four lanes of a point
-// end with the same result.
-__device__ __forceinline__ void top2_merge(Top2& t, int o) {
-    const float ob1 = lane_xor(t.b1, o);
-    const float ob2 = lane_xor(t.b2, o);
-    const float ob3 = lane_xor(t.b3, o);
-    const int oa1 = lane_xor(t.a1, o);
-    const int oa2 = lane_xor(t.a2, o);
-    const bool other = ob1 < t.b1 || (ob1 == t.b1 && oa1 < t.a1);
-    // winner list W = (w1, w2, w3), loser list L = (l1, l2, l3); merged:
-    // first w1; second min(w2, l1); third the next of the two lists
-    const float w2 = other ? ob2 : t.b2, w3 = other ? ob3 : t.b3;
-    const float l1 = other ? t.b1 : ob1, l2 = other ? t.b2 : ob2;
-    const int wa2 = other ? oa2 : t.a2, la1 = other ? t.a1 : oa1;
-    const bool l_second = l1 < w2 || (l1 == w2 && la1 < wa2);
-    t.b1 = other ? ob1 : t.b1;
-    t.a1 = other ? oa1 : t.a1;
-    t.b2 = l_second ? l1 : w2;
-    t.a2 = l_second ? la1 : wa2;
-    t.b3 = l_second ? fminf(w2, l2) : fminf(w3, l1);
+// sets, so keys are distinct and both lanes end with the same triple).  The
+// other triple is ascending: its second key ranks second at best, its third
+// third at best.
+__device__ __forceinline__ void top3_merge(Top3& t, int o) {
+    const unsigned o1 = (unsigned)lane_xor((int)t.t1, o);
+    const unsigned o2 = (unsigned)lane_xor((int)t.t2, o);
+    const unsigned o3 = (unsigned)lane_xor((int)t.t3, o);
+    top3_insert(t, o1);
+    const unsigned c = max(t.t2, o2);
+    t.t2 = min(t.t2, o2);
+    t.t3 = min(min(t.t3, c), o3);
 }
 
-// Scores of this lane's point against all nblk*16 centroids; returns the
-// merged best/runner-up for the point (identical in its four lanes).
+__device__ __forceinline__ unsigned key_index(unsigned key, unsigned kmask) { return key & kmask; }
+__device__ __forceinline__ float key_value(unsigned key, unsigned kmask) {
+    return __uint_as_float(key & ~kmask);
+}
+
+// Index bits for nblk blocks of 16 centroids, and the certificate's
+// quantisation factor 2^(NB - 20).
+__device__ __forceinline__ void key_params(int nblk, unsigned* kmask, float* qscale) {
+    int nb = 4;
+    while ((1 << nb) < nblk * 16) ++nb;
+    *kmask = (1u << nb) - 1u;
+    *qscale = __builtin_ldexpf(1.0f, nb - 20);
+}
+
+// Keys of this lane's point against all nblk*16 centroids; returns the
+// merged three best (identical in the point's four lanes).  xn2: the
+// point's FP32 |x|^2.
 template <int D, int PREC>
-__device__ __forceinline__ Top2 screen_tile(const float (&xq)[Lay<D>::DL],
+__device__ __forceinline__ Top3 screen_tile(const float (&xq)[Lay<D>::DL],
                                             const void* __restrict__ aop,
-                                            const float* __restrict__ nrm, int nblk) {
+                                            const float* __restrict__ nrm, int nblk, float xn2,
+                                            unsigned kmask) {
     constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
     const int lane = threadIdx.x & 63, g = lane >> 4;
-    Top2 t{__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), 0, 0};
+    Top3 t{~0u, ~0u, ~0u};
     if constexpr (PREC == kPrecF32) {
         const float* a = static_cast<const float*>(aop);
         for (int blk = 0; blk < nblk; ++blk) {
@@ -184,7 +212,8 @@ __device__ __forceinline__ Top2 screen_tile(const float (&xq)[Lay<D>::DL],
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
                                                            acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) top2_push(t, acc[r], blk * 16 + 4 * g + r);
+            for (int r = 0; r < 4; ++r)
+                top3_insert(t, screen_key(acc[r] + xn2, kmask, (unsigned)(blk * 16 + 4 * g + r)));
         }
     } else {
         bf16x8 xb[KC];
@@ -203,11 +232,12 @@ __device__ __forceinline__ Top2 screen_tile(const float (&xq)[Lay<D>::DL],
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[(blk * KC + kc) * 64 + lane], xb[kc],
                                                               acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) top2_push(t, acc[r], blk * 16 + 4 * g + r);
+            for (int r = 0; r < 4; ++r)
+                top3_insert(t, screen_key(acc[r] + xn2, kmask, (unsigned)(blk * 16 + 4 * g + r)));
         }
     }
-    top2_merge(t, 16);
-    top2_merge(t, 32);
+    top3_merge(t, 16);
+    top3_merge(t, 32);
     return t;
 }
 
@@ -245,18 +275,22 @@ __device__ __forceinline__ double quarter_dist64(const float (&xq)[Lay<D>::DL],
 // factor of the test covers its error.
 __device__ __forceinline__ float cert_norm(float n2) { return __builtin_amdgcn_sqrtf(n2); }
 
-// Screening winner certified?  gap > 2.5 E with E = ea |x| + eb (alpha and
-// beta already multiplied by cmax and cmax^2).
-__device__ __forceinline__ bool certified(const Top2& t, float xnorm, float ea, float eb) {
-    if (!(t.b2 < __builtin_huge_valf())) return true;
-    return (t.b2 - t.b1) > 2.5f * (ea * xnorm + eb);
+// Screening winner certified (see the certificate above)?  E = ea |x| +
+// eb (alpha and beta already multiplied by cmax and cmax^2).
+__device__ __forceinline__ bool certified(const Top3& t, unsigned kmask, float qscale, float xnorm,
+                                          float ea, float eb) {
+    if (t.t2 >= 0x7F800000u) return true;  // fewer than two valid centroids
+    const float q1 = key_value(t.t1, kmask), q2 = key_value(t.t2, kmask);
+    return (q2 - q1) > 2.5f * (ea * xnorm + eb) + qscale * q2;
 }
 
 // The exact argmin is one of the two best screened centroids when the third
-// is separated from the best by the certificate.
-__device__ __forceinline__ bool top2_suffices(const Top2& t, float xnorm, float ea, float eb) {
-    if (!(t.b3 < __builtin_huge_valf())) return true;
-    return (t.b3 - t.b1) > 2.5f * (ea * xnorm + eb);
+// is separated from the best by the same margin.
+__device__ __forceinline__ bool top2_suffices(const Top3& t, unsigned kmask, float qscale,
+                                              float xnorm, float ea, float eb) {
+    if (t.t3 >= 0x7F800000u) return true;
+    const float q1 = key_value(t.t1, kmask), q3 = key_value(t.t3, kmask);
+    return (q3 - q1) > 2.5f * (ea * xnorm + eb) + qscale * q3;
 }
 
 // Exact FP64 decision for the points of this wave whose screening was not
