@@ -509,6 +509,8 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         a2 < k ? a2 : a1, L.C64, k);
                     if (valid) {
                         // this lane's share of the objective and of the sums
+                        // (padded coordinates are zero in the gathered rows,
+                        // so their sums stay exactly zero)
                         const double* cr = L.C64 + am * CS + g * DL;
                         double* ps = pw + am * CS + g * DL;
                         double part = 0.0;
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                             const double xd = (double)xq[t];
                             const double e = xd - cr[t];
                             part = __fma_rn(e, e, part);
-                            if (g * DL + t < d) atomicAdd(ps + t, xd);
+                            atomicAdd(ps + t, xd);
                         }
                         fl += part;
                         if (g == 0) {

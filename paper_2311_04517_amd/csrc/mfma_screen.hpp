@@ -155,13 +155,19 @@ __device__ __forceinline__ unsigned screen_key(float v, unsigned kmask, unsigned
     return (pos & ~kmask) | j;
 }
 
-// Insert a key into the ascending triple (compare-exchange chain).
+// Median of three (one v_med3_u32).
+__device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
+    return max(min(a, b), min(max(a, b), c));
+}
+
+// Insert a key into the ascending triple: the new i-th smallest of
+// {t1, t2, t3, key} is min(t1, key), med3(t1, t2, key), med3(t2, t3, key).
 __device__ __forceinline__ void top3_insert(Top3& t, unsigned key) {
-    const unsigned c1 = max(t.t1, key);
+    const unsigned n3 = umed3(t.t2, t.t3, key);
+    const unsigned n2 = umed3(t.t1, t.t2, key);
     t.t1 = min(t.t1, key);
-    const unsigned c2 = max(t.t2, c1);
-    t.t2 = min(t.t2, c1);
-    t.t3 = min(t.t3, c2);
+    t.t2 = n2;
+    t.t3 = n3;
 }
 
 // Merge with the lane at XOR distance o (the lanes hold disjoint centroid
@@ -173,9 +179,9 @@ __device__ __forceinline__ void top3_merge(Top3& t, int o) {
     const unsigned o2 = (unsigned)lane_xor((int)t.t2, o);
     const unsigned o3 = (unsigned)lane_xor((int)t.t3, o);
     top3_insert(t, o1);
-    const unsigned c = max(t.t2, o2);
+    const unsigned n3 = umed3(t.t2, t.t3, o2);
     t.t2 = min(t.t2, o2);
-    t.t3 = min(min(t.t3, c), o3);
+    t.t3 = min(n3, o3);
 }
 
 __device__ __forceinline__ unsigned key_index(unsigned key, unsigned kmask) { return key & kmask; }
