@@ -345,7 +345,8 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     const size_t desc_b = (size_t)n * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n * 4;
     const size_t sbuf_b = (size_t)idx_len * D * 4;
-    const size_t need = Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 8});
+    const size_t need =
+        Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 8, (size_t)idx_len * 4});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
@@ -353,6 +354,7 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     int32_t* queue = static_cast<int32_t*>(cv.take(256));
     float* sbuf = static_cast<float*>(cv.take(sbuf_b));
     double* d2 = static_cast<double*>(cv.take((size_t)idx_len * 8));
+    int32_t* lbuf = static_cast<int32_t*>(cv.take((size_t)idx_len * 4));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
     memcpy(host.data() + desc_b, order.data(), order_b);
@@ -374,6 +376,7 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     a.labels_out = labels_out;
     a.sbuf = sbuf;
     a.d2buf = d2;
+    a.lbuf = lbuf;
     a.queue = queue;
     a.kmax = kmax;
     a.seed_only = seed_only;
@@ -406,6 +409,7 @@ struct hpc_plan_s {
     int32_t* queue = nullptr;
     float* sbuf = nullptr;
     double* d2 = nullptr;
+    int32_t* lbuf = nullptr;
     float* tC = nullptr;  // autotuner scratch
     double* tf = nullptr;
     int32_t* tit = nullptr;
@@ -453,6 +457,7 @@ hpc::LloydArgs plan_args(hpc_plan p, const float* X, int64_t m, const int64_t* i
     a.labels_out = labels_out;
     a.sbuf = p->sbuf;
     a.d2buf = p->d2;
+    a.lbuf = p->lbuf;
     a.queue = p->queue;
     a.kmax = p->kmax;
     a.n_cand = 3;
@@ -710,8 +715,9 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     const size_t order_b = (size_t)n_samples * 8;
     const size_t sbuf_b = (size_t)idx_len * p->D * 4;
     const size_t d2_b = (size_t)idx_len * 8;
-    const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)c_len * 4,
-                                     (size_t)n_samples * 8, (size_t)n_samples * 4});
+    const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)idx_len * 4,
+                                     (size_t)c_len * 4, (size_t)n_samples * 8,
+                                     (size_t)n_samples * 4});
     hipError_t e = hipMalloc(&p->mem, need);
     if (e != hipSuccess) {
         p->mem = nullptr;
@@ -725,6 +731,7 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     p->queue = static_cast<int32_t*>(cv.take(256));
     p->sbuf = static_cast<float*>(cv.take(sbuf_b));
     p->d2 = static_cast<double*>(cv.take(d2_b));
+    p->lbuf = static_cast<int32_t*>(cv.take((size_t)idx_len * 4));
     p->tC = static_cast<float*>(cv.take((size_t)c_len * 4));
     p->tf = static_cast<double*>(cv.take((size_t)n_samples * 8));
     p->tit = static_cast<int32_t*>(cv.take((size_t)n_samples * 4));

@@ -44,6 +44,7 @@ struct LloydArgs {
     int32_t* labels_out;
     float* sbuf;    // gathered samples, indexed by idx_offset, stride D
     double* d2buf;  // D^2, indexed by idx_offset
+    int32_t* lbuf;  // label of each sample point in the previous pass, by idx_offset
     int32_t* queue;
     int32_t kmax;
     int32_t n_copies;  // partial-sum copies in LDS (== waves: private per wave)
@@ -70,9 +71,8 @@ struct Smem {
     void* aop;     // MFMA A operands, nblk x ... (see mfma_screen.hpp)
     float* nrm;    // nblk*16 score biases |c|^2
     double* crow;  // 4 x D candidate rows
-    double* psum;  // n_copies x kmax rows (stride CS) of update sums (union with seeding scan)
+    double* psum;  // n_copies x kmax rows (stride CS) of running update sums
     int* pcnt;     // n_copies x kmax counts
-    double* incl;  // NT inclusive scan of chunk sums   (seeding)
     double* red;   // 4 x NW wave partials
     double* cn;    // kmax squared centroid norms
     int* deg;      // kmax degenerate-row list
@@ -82,9 +82,7 @@ struct Smem {
     static __host__ __device__ int nblk_of(int kmax) { return (kmax + 15) / 16; }
 
     static __host__ __device__ size_t union_bytes(int kmax, int copies) {
-        size_t lloyd = (size_t)copies * kmax * Lay<D>::CS * 8 + align_up((size_t)copies * kmax * 4, 16);
-        size_t seed = (size_t)NT * 8;
-        return lloyd > seed ? lloyd : seed;
+        return (size_t)copies * kmax * Lay<D>::CS * 8 + align_up((size_t)copies * kmax * 4, 16);
     }
     static __host__ __device__ size_t bytes(int kmax, int copies) {
         const int nb = nblk_of(kmax);
@@ -109,7 +107,6 @@ struct Smem {
         p += 4 * D * 8;
         psum = reinterpret_cast<double*>(p);
         pcnt = reinterpret_cast<int*>(p + (size_t)copies * kmax * Lay<D>::CS * 8);
-        incl = reinterpret_cast<double*>(p);
         p += union_bytes(kmax, copies);
         red = reinterpret_cast<double*>(p);
         p += 4 * NW * 8;
@@ -140,24 +137,6 @@ __device__ __forceinline__ void block_sum_n(double (&v)[NV], double* red) {
         for (int i = 0; i < NW; ++i) t += red[q * NW + i];
         v[q] = t;
     }
-    __syncthreads();
-}
-
-// Inclusive scan of one double per thread over the workgroup (fixed order).
-// Result written to out[tid]; two barriers.
-template <int NT>
-__device__ __forceinline__ void block_incl_scan(double v, double* out, double* red) {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const double u = __shfl_up(v, o, kWave);
-        if (lane >= o) v += u;
-    }
-    if (lane == kWave - 1) red[w] = v;
-    __syncthreads();
-    double base = 0.0;
-    for (int i = 0; i < w; ++i) base += red[i];
-    out[threadIdx.x] = base + v;
     __syncthreads();
 }
 
@@ -414,6 +393,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         const int nblk = (k + 15) / 16;
         float* Sg = a.sbuf + (size_t)ds.idx_offset * D;
         double* d2 = a.d2buf + ds.idx_offset;
+        int32_t* lprev = a.lbuf + ds.idx_offset;
         const SampleView<D> sv{Sg};
 
         // gather the sample rows (zero padded to D): consecutive threads
@@ -478,8 +458,13 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 const double cmax = centroid_max_norm<D, NT, PREC>(L, k, d);
                 const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
                 build_operands<D, PREC, NT>(L.C64, k, d, nblk, L.aop, L.nrm);
-                for (int e = tid; e < copies * k * CS; e += NT) L.psum[e] = 0.0;
-                for (int e = tid; e < copies * k; e += NT) L.pcnt[e] = 0;
+                // the sums and counts run across passes: the first pass adds
+                // every point, later passes only the points whose label changed
+                const bool first = it == 0;
+                if (first) {
+                    for (int e = tid; e < copies * k * CS; e += NT) L.psum[e] = 0.0;
+                    for (int e = tid; e < copies * k; e += NT) L.pcnt[e] = 0;
+                }
                 __syncthreads();
                 double* pw = L.psum + (size_t)(wid % copies) * k * CS;
                 int* cw = L.pcnt + (wid % copies) * k;
@@ -489,14 +474,16 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // flight while one tile is processed (unrolled by three so
                 // that no buffer with a load in flight is ever copied)
                 float xa[DL], xb[DL], xc[DL];
+                int la, lb, lc;
                 // branch-free: rows past the end re-read the last row (their
                 // lanes are masked in process), which keeps the memory
                 // counters exact for the compiler's wait placement
-                auto fetch = [&](int tile, float (&dst)[DL]) {
+                auto fetch = [&](int tile, float (&dst)[DL], int& old) {
                     const int i = min(tile * 16 + pl, s - 1);
                     load_quarter<D>(Sg + (size_t)i * D, g, dst);
+                    old = lprev[i];
                 };
-                auto process = [&](int tile, const float (&xq)[DL]) {
+                auto process = [&](int tile, const float (&xq)[DL], int old) {
                     const int i = tile * 16 + pl;
                     const bool valid = i < s;
                     const float xn2 = point_norm2<D>(xq);
@@ -508,37 +495,48 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb), a1,
                         a2 < k ? a2 : a1, L.C64, k);
                     if (valid) {
-                        // this lane's share of the objective and of the sums
-                        // (padded coordinates are zero in the gathered rows,
-                        // so their sums stay exactly zero)
+                        // this lane's share of the objective; a point that
+                        // changed cluster moves its coordinates between the
+                        // running sums (padded coordinates are zero in the
+                        // gathered rows, so their sums stay exactly zero)
                         const double* cr = L.C64 + am * CS + g * DL;
-                        double* ps = pw + am * CS + g * DL;
                         double part = 0.0;
 #pragma unroll
                         for (int t = 0; t < DL; ++t) {
-                            const double xd = (double)xq[t];
-                            const double e = xd - cr[t];
+                            const double e = (double)xq[t] - cr[t];
                             part = __fma_rn(e, e, part);
-                            atomicAdd(ps + t, xd);
                         }
                         fl += part;
-                        if (g == 0) {
-                            if (a.labels_out) a.labels_out[ds.idx_offset + i] = am;
-                            atomicAdd(cw + am, 1);
+                        const int prev = first ? -1 : old;
+                        if (am != prev) {
+                            double* pn = pw + am * CS + g * DL;
+#pragma unroll
+                            for (int t = 0; t < DL; ++t) atomicAdd(pn + t, (double)xq[t]);
+                            if (prev >= 0) {
+                                double* po = pw + prev * CS + g * DL;
+#pragma unroll
+                                for (int t = 0; t < DL; ++t) atomicAdd(po + t, -(double)xq[t]);
+                            }
+                            if (g == 0) {
+                                atomicAdd(cw + am, 1);
+                                if (prev >= 0) atomicAdd(cw + prev, -1);
+                                lprev[i] = am;
+                            }
                         }
+                        if (g == 0 && a.labels_out) a.labels_out[ds.idx_offset + i] = am;
                     }
                 };
-                fetch(wid, xa);
-                fetch(wid + NW, xb);
+                fetch(wid, xa, la);
+                fetch(wid + NW, xb, lb);
                 for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
-                    fetch(tile + 2 * NW, xc);
-                    process(tile, xa);
+                    fetch(tile + 2 * NW, xc, lc);
+                    process(tile, xa, la);
                     if ((tile + NW) * 16 >= s) break;
-                    fetch(tile + 3 * NW, xa);
-                    process(tile + NW, xb);
+                    fetch(tile + 3 * NW, xa, la);
+                    process(tile + NW, xb, lb);
                     if ((tile + 2 * NW) * 16 >= s) break;
-                    fetch(tile + 4 * NW, xb);
-                    process(tile + 2 * NW, xc);
+                    fetch(tile + 4 * NW, xb, lb);
+                    process(tile + 2 * NW, xc, lc);
                 }
                 f = block_sum<NT>(fl, L.red);
                 ++it;
