@@ -117,20 +117,9 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
     key_params(nblk, &kmask, &qscale);
     double fl = 0.0;
     const int64_t n_tiles = (m + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * NW + wid; tile < n_tiles;
-         tile += (int64_t)gridDim.x * NW) {
+    auto process = [&](int64_t tile, const float (&xq)[DL]) {
         const int64_t i = tile * 16 + (lane & 15);
         const bool valid = i < m;
-        float xq[DL];
-        if (valid && vec) {
-            load_quarter<D>(X + i * D, g, xq);
-        } else {
-#pragma unroll
-            for (int t = 0; t < DL; ++t) {
-                const int dim = g * DL + t;
-                xq[t] = (valid && dim < d) ? X[i * d + dim] : 0.f;
-            }
-        }
         const float xn2 = point_norm2<D>(xq);
         const Top3 t3 = screen_tile<D, PREC>(xq, aop, nrm, nblk, xn2, kmask);
         const float xn = cert_norm(xn2);
@@ -146,6 +135,41 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
                 if (labels) labels[i] = am;
                 if (counts && am >= 0) atomicAdd(&hist[am], 1);
             }
+        }
+    };
+    const int64_t first = (int64_t)blockIdx.x * NW + wid, stride = (int64_t)gridDim.x * NW;
+    if (vec) {
+        // rows of D floats, 16-byte aligned: software pipelined over three
+        // register buffers (rows of the next two tiles in flight while one
+        // is processed); rows past the end re-read the last row, branch-free
+        auto fetch = [&](int64_t tile, float (&dst)[DL]) {
+            int64_t i = tile * 16 + (lane & 15);
+            i = i < m ? i : m - 1;
+            load_quarter<D>(X + i * D, g, dst);
+        };
+        float xa[DL], xb[DL], xc[DL];
+        fetch(first, xa);
+        fetch(first + stride, xb);
+        for (int64_t tile = first; tile < n_tiles; tile += 3 * stride) {
+            fetch(tile + 2 * stride, xc);
+            process(tile, xa);
+            if (tile + stride >= n_tiles) break;
+            fetch(tile + 3 * stride, xa);
+            process(tile + stride, xb);
+            if (tile + 2 * stride >= n_tiles) break;
+            fetch(tile + 4 * stride, xb);
+            process(tile + 2 * stride, xc);
+        }
+    } else {
+        for (int64_t tile = first; tile < n_tiles; tile += stride) {
+            const int64_t i = tile * 16 + (lane & 15);
+            float xq[DL];
+#pragma unroll
+            for (int t = 0; t < DL; ++t) {
+                const int dim = g * DL + t;
+                xq[t] = (i < m && dim < d) ? X[i * d + dim] : 0.f;
+            }
+            process(tile, xq);
         }
     }
     const double tot = block_sum<NT>(fl, red);

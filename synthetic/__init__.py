@@ -79,7 +79,14 @@ def gaussian_mixture(m: int, d: int, n_comp: int, *, seed: int, centre_box: floa
         c = torch.multinomial(w_d, n, replacement=True, generator=g)
         z = torch.randn(n, d, generator=g, device=device, dtype=torch.float32) * sig_d[c]
         if rot_d is not None:
-            z = torch.bmm(rot_d[c], z.unsqueeze(2)).squeeze(2)
+            # rotate each component's offsets by its own matrix (grouped, so
+            # no per-point d x d matrix is ever materialised)
+            zr = torch.empty_like(z)
+            for q in range(n_comp):
+                sel = (c == q).nonzero(as_tuple=True)[0]
+                if sel.numel():
+                    zr[sel] = z[sel] @ rot_d[q].T
+            z = zr
         x = cen_d[c] + z
         if noise_frac > 0:
             is_noise = torch.rand(n, generator=g, device=device) < noise_frac
