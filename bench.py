@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="MFMA type of the distance screening (decisions are FP64-exact)")
+    ap.add_argument("--no-other-precision", dest="other_precision", action="store_false",
+                    help="skip the same measurement with the other screening precision")
     ap.add_argument("--no-tts", dest="tts", action="store_false",
                     help="skip the time-to-SSE comparison")
     ap.add_argument("--tts-samples", type=int, default=64,
@@ -88,6 +90,83 @@ def main():
         pmc_target(api, X, m, d, W, s, k, prec, args.seed)
         return
 
+    main_res = run_metric(api, X, args, prec)
+    other = None
+    if args.other_precision:
+        oprec = api.PREC_FP32 if prec == api.PREC_BF16_MFMA else api.PREC_BF16_MFMA
+        other = run_metric(api, X, args, oprec)
+    value, elapsed, passes = main_res["value"], main_res["elapsed"], main_res["passes"]
+    t_lloyd, t_assign = main_res["t_lloyd"], main_res["t_assign"]
+    lloyd_gbs, assign_gbs, tune = main_res["lloyd_gbs"], main_res["assign_gbs"], main_res["tune"]
+    C_before, r_first_timed = main_res["C_before"], main_res["r_first_timed"]
+
+    # HBM traffic per launch from the committed counter measurement, scaled
+    # to this launch's units of work (null if the kernels changed since)
+    traffic = None
+    rec = measured_traffic(f"lloyd_resident_metric_traffic_{'bf16' if prec else 'fp32'}.json")
+    if rec is not None:
+        units = float(passes.mean()) * s
+        traffic = {"bytes_per_launch": rec["bytes_per_unit"] * units,
+                   "read_bytes_per_unit": rec["read_bytes_per_unit"],
+                   "write_bytes_per_unit": rec["write_bytes_per_unit"],
+                   "algorithmic_bytes_per_unit": 4 * d, "source": rec["file"]}
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(X, C_before, r_first_timed, args, m, d, W, s, k)
+    tts = None
+    if args.tts:
+        f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
+        tts = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
+
+    out = {
+        "metric": "sample-point-iters/sec (k=25,d=32)",
+        "value": value,
+        "unit": "sample-point-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "fp32" else "bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": "gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round",
+                   "m": m, "d": d, "k": k, "s": s, "workers": W, "strategy": "competitive",
+                   "passes_per_step": float(passes.mean())},
+        "roofline": {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"k_lloyd_resident<32,256,{prec}>", "launch": tune,
+                     "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
+                     "avg_launch_ms": t_lloyd * 1e3},
+        "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,
+                       "frac": assign_gbs / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+        "time_to_sse": tts,
+    }
+    if other is not None:
+        out["other_screening"] = {
+            "dtype": "bf16+f64" if prec == api.PREC_FP32 else "f32+f64",
+            "value": other["value"], "ms_per_step": other["elapsed"] / args.steps * 1e3,
+            "lloyd_avg_launch_ms": other["t_lloyd"] * 1e3, "lloyd_gbs": other["lloyd_gbs"],
+            "lloyd_frac": other["lloyd_gbs"] / HBM_PEAK_GBS,
+            "assign_avg_launch_ms": other["t_assign"] * 1e3, "assign_gbs": other["assign_gbs"],
+            "launch": other["tune"],
+            "same_passes": bool((other["passes"] == passes).all()),
+            "note": "same workload and seeds; decisions are FP64-exact in both screenings, so "
+                    "pass counts and results agree"}
+    print(json.dumps(out), flush=True)
+
+
+def run_metric(api, X, args, prec):
+    """The timed competitive rounds (see the module docstring) with one
+    screening precision: autotune, warm up, time args.steps rounds."""
+    import numpy as np
+    import torch
+
+    dev = X.device
+    m, d = X.shape
+    W, s, k = args.workers, args.s, args.k
     C_inc = torch.full((W, k, d), float("nan"), dtype=torch.float32, device=dev)
     f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device=dev)
     C = torch.empty_like(C_inc)
@@ -112,12 +191,13 @@ def main():
         Ct = torch.full((c_len,), float("nan"), device=dev)
         plan.lloyd(X, idx, Ct)  # converged start, so the timed passes are warm ones
         tune, ms = tuning.tuned(plan, X, idx, Ct, max_iter=3, retune=True)
-        print(f"[bench] autotuned {tune} ({ms:.3f} ms for 3 passes)", file=sys.stderr, flush=True)
+        print(f"[bench] precision {prec}: autotuned {tune} ({ms:.3f} ms for 3 passes)",
+              file=sys.stderr, flush=True)
         del Ct
 
     ev = {name: [] for name in ("lloyd", "assign")}
 
-    def step(r, timed):
+    def step(timed):
         plan.draw(m, idx)
         C.copy_(C_inc)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -138,80 +218,46 @@ def main():
             ev["assign"].append((e2, e3))
         return it.clone()
 
-    r = 0
     for _ in range(args.warmup):
-        step(r, False)
-        r += 1
+        step(False)
     torch.cuda.synchronize()
     print(f"[bench] {args.warmup} warmup step(s) done", file=sys.stderr, flush=True)
     its = []
-    f_before = f_inc.clone()
     C_before = C_inc.clone()
-    r_first_timed = r
+    r_first_timed = args.warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        its.append(step(r, True))
-        r += 1
+        its.append(step(True))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     passes = np.array([int(t.sum().item()) for t in its])
     spi = int(passes.sum()) * s
-    value = spi / elapsed
     t_lloyd = np.mean([a.elapsed_time(b) for a, b in ev["lloyd"]]) / 1e3
     t_assign = np.mean([a.elapsed_time(b) for a, b in ev["assign"]]) / 1e3
     spi_per_step = passes.mean() * s
     lloyd_gbs = spi_per_step * 4 * d / t_lloyd / 1e9
     assign_gbs = (m * 4 * d + m * 4) / t_assign / 1e9
-    print(f"[bench] {args.steps} steps in {elapsed:.3f}s; passes/step {passes.tolist()}; "
-          f"lloyd {t_lloyd * 1e3:.2f} ms ({lloyd_gbs:.0f} GB/s algorithmic), "
+    print(f"[bench] precision {prec}: {args.steps} steps in {elapsed:.3f}s; passes/step "
+          f"{passes.tolist()}; lloyd {t_lloyd * 1e3:.2f} ms ({lloyd_gbs:.0f} GB/s algorithmic), "
           f"assign {t_assign * 1e3:.3f} ms ({assign_gbs:.0f} GB/s), SSE {sse.item():.6e}",
           file=sys.stderr, flush=True)
-
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(X, C_before, r_first_timed, args, m, d, W, s, k)
-    tts = None
-    if args.tts:
-        plan.close()
-        f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
-        tts = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
-
-    out = {
-        "metric": "sample-point-iters/sec (k=25,d=32)",
-        "value": value,
-        "unit": "sample-point-iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "fp32" else "bf16+f64",
-        "data": "synthetic",
-        "config": {"workload": "gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round",
-                   "m": m, "d": d, "k": k, "s": s, "workers": W, "strategy": "competitive",
-                   "passes_per_step": float(passes.mean())},
-        "roofline": {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_lloyd_resident<32,256,{prec}>", "launch": tune,
-                     "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
-                     "avg_launch_ms": t_lloyd * 1e3},
-        "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,
-                       "frac": assign_gbs / HBM_PEAK_GBS},
-        "cpu_baseline": cpu,
-        "time_to_sse": tts,
-    }
-    print(json.dumps(out), flush=True)
+    plan.close()
+    return dict(value=spi / elapsed, elapsed=elapsed, passes=passes, t_lloyd=t_lloyd,
+                t_assign=t_assign, lloyd_gbs=lloyd_gbs, assign_gbs=assign_gbs, tune=tune,
+                C_before=C_before, r_first_timed=r_first_timed, sse=sse.item())
 
 
 def pmc_target(api, X, m, d, W, s, k, prec, seed):
-    """One launch of each kernel, for hardware-counter collection: a 1 GiB
-    device copy whose counter readings calibrate the traffic counters, a
-    cold batch (K-means++ seeding and passes to the stop rule), a warm batch
-    of exactly 3 passes, and one full assignment."""
+    """One launch of each kernel as the benchmark runs it, for
+    hardware-counter collection: a 1 GiB device copy whose counter readings
+    calibrate the traffic counters, a cold batch (K-means++ seeding and
+    passes to the stop rule), the autotuned plan's warm batch of exactly 3
+    passes from the cold batch's centroids on fresh samples, and one full
+    assignment."""
     import torch
+
+    from paper_2311_04517_amd import tuning
 
     src = torch.ones(1 << 28, dtype=torch.float32, device=X.device)
     dst = torch.empty_like(src)
@@ -219,15 +265,38 @@ def pmc_target(api, X, m, d, W, s, k, prec, seed):
     torch.cuda.synchronize()
     del src, dst
     desc, idx_len, c_len = api.make_desc([s] * W, [k] * W, seed=seed, sample_id=range(W), d=d)
-    idx = api.draw_samples(m, desc, idx_len)
+    plan = api.Plan(d, desc, idx_len, c_len, precision=prec)
+    idx = torch.empty(idx_len, dtype=torch.int64, device=X.device)
+    plan.draw(m, idx)
     C = torch.full((c_len,), float("nan"), device=X.device)
-    api.lloyd_batch(X, idx, desc, C, precision=prec)
-    desc2, _, _ = api.make_desc([s] * W, [k] * W, seed=seed, sample_id=range(W, 2 * W), d=d)
-    idx2 = api.draw_samples(m, desc2, idx_len)
-    api.lloyd_batch(X, idx2, desc2, C, max_iter=3, rel_tol=0.0, precision=prec)
+    plan.lloyd(X, idx, C)
+    tuning.tuned(plan, X, idx, C, max_iter=3, retune=True)
+    plan.advance(W)
+    plan.draw(m, idx)
+    torch.cuda.synchronize()
+    print("[bench] pmc target: warm batch next", file=sys.stderr, flush=True)
+    plan.lloyd(X, idx, C, max_iter=3, rel_tol=0.0)
     api.assign_sse(X, C[: k * d].view(k, d).contiguous(), precision=prec)
     torch.cuda.synchronize()
+    plan.close()
     print("[bench] pmc target done", file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel_file):
+    """HBM bytes per unit of work measured with hardware counters for the
+    current kernel sources (profiles/<kernel_file>), or None when the sources
+    changed since the counters were taken."""
+    from paper_2311_04517_amd import build
+
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != build.source_digest():
+        return None
+    return rec
 
 
 def _first_reach(api, X, hist, times, target, precision):

@@ -24,6 +24,19 @@ FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 over the HIP sources and headers the library is built from
+    (identifies the kernels a profile was taken on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(SOURCES + HEADERS):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, extra=None) -> str:
     cmd = [HIPCC, *FLAGS, *(extra or []), *SOURCES, "-o", OUT + ".tmp"]
     if verbose:
