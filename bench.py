@@ -430,9 +430,10 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
 
 
 def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
-    """The FP64 oracle on a bounded sample of the same workload: the first
-    samples of the first timed round, from the same incumbents, on the
-    host's cores (samples run side by side)."""
+    """The FP64 oracle on a bounded sample of the same workload: samples of
+    the first timed round and the rounds after it, from the incumbents the
+    timed round started from, on the host's cores (samples run side by
+    side), for about args.cpu_seconds of CPU work."""
     import numpy as np
 
     import oracle
@@ -440,12 +441,16 @@ def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
 
     n_threads = max(1, min(16, os.cpu_count() or 1))
     Xn = X.cpu().numpy()
+    C_host = C_start.double().cpu().numpy()
     done_spi, done_t, done_n = 0, 0.0, 0
     per = n_threads
-    while done_t < args.cpu_seconds and done_n + per <= W:
+    # the timed round's samples, then the next rounds' (each from its
+    # worker's incumbent at the start of the timed round), in groups of
+    # n_threads samples until the time budget is spent
+    while done_t < args.cpu_seconds and done_n < 64 * W:
         ids = [r * W + w for w in range(done_n, done_n + per)]
         idx = np.concatenate([oracle.draw_sample(m, s, args.seed, i) for i in ids])
-        Cb = C_start[done_n:done_n + per].double().cpu().numpy().ravel().copy()
+        Cb = np.concatenate([C_host[i % W].ravel() for i in range(done_n, done_n + per)])
         desc = dict(idx_offset=np.arange(per) * s, s=[s] * per, k=[k] * per,
                     c_offset=np.arange(per) * k * d, seed=[args.seed] * per, sample_id=ids)
         t0 = time.perf_counter()
@@ -456,8 +461,9 @@ def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
     del api
     out = {"value": done_spi / done_t, "unit": "sample-point-iters/s", "cores": n_threads,
            "kind": "oracle",
-           "sample": f"{done_n} of the {W} samples of one round (same inputs and incumbents), "
-                     f"{done_t:.1f}s of CPU work on {n_threads} threads"}
+           "sample": f"{done_n} samples of the workload (the timed round's first, then the next "
+                     f"rounds', each from its worker's incumbent at the start of the timed "
+                     f"round), {done_t:.1f}s of CPU work on {n_threads} threads"}
     if args.tts:
         # the time-to-SSE threshold: the single-worker method (one worker,
         # keep-the-best over N samples, then the full assignment), FP64

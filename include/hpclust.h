@@ -33,7 +33,13 @@
  *  - Scratch.  The library keeps a grow-only scratch workspace per device
  *    and stream, allocated on first use (hipMalloc) and freed by
  *    hpc_release().  Calls on different streams may run concurrently.
- *  - Supported sizes: 1 <= d <= 128, 1 <= k <= 512, k <= s, m < 2^62.
+ *  - Supported sizes: 1 <= d <= 128, 1 <= k <= 512, k <= s, m < 2^62, and
+ *    the k centroids (FP64, with the per-cluster sums for Lloyd) must fit a
+ *    workgroup's 160 KiB of LDS.  Largest k per padded d (8, 16, 32, 64,
+ *    128) for Lloyd: 512, 456, 240, 121, 60 (FP32 screening), 512, 456, 264,
+ *    135, 66 (BF16); for hpc_assign_sse: 512, 512, 400, 207, 101 (FP32),
+ *    512, 512, 480, 246, 125 (BF16).  Larger combinations are refused with
+ *    HPC_ERR_UNSUPPORTED before anything is launched.
  */
 #ifndef HPCLUST_H
 #define HPCLUST_H

@@ -25,15 +25,20 @@ FLAGS = [
 
 
 def source_digest() -> str:
-    """SHA-256 over the HIP sources and headers the library is built from
-    (identifies the kernels a profile was taken on)."""
+    """SHA-256 over the code of the HIP sources and headers under csrc/,
+    comments and whitespace removed (identifies the kernels a profile was
+    taken on; documentation edits leave it unchanged)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
-    for f in sorted(SOURCES + HEADERS):
+    for f in sorted(p for p in SOURCES + HEADERS if os.path.dirname(p) == CSRC):
+        with open(f) as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

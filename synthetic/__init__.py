@@ -175,3 +175,29 @@ def mixture_family(n_sets: int, s: int, *, d: int = 32, n_comp: int = 25, seed: 
     sets = torch.arange(n_sets, device=device).unsqueeze(1).expand(n_sets, s)
     X = cen[sets, lab] + sig[sets, lab] * torch.randn(n_sets, s, d, **kw)
     return X.reshape(n_sets * s, d).contiguous(), cen
+
+
+def scaling_blobs(i: int, *, seed: int = 0, device="cpu") -> Mixture:
+    """The scaling study's data (Section 6.8): m = 3^(i+7) points in 10
+    dimensions from 10 Gaussian blobs with centres uniform in (-40, 40)^10
+    and isotropic std uniform in (0, 10), plus 500 points uniform in
+    (-50, 50)^10 as noise (appended after the blob points, component -1)."""
+    m = 3 ** (i + 7)
+    d, n_comp = 10, 10
+    gc = _gen(seed, "cpu")
+    centres = (torch.rand(n_comp, d, generator=gc, dtype=torch.float64) * 2 - 1) * 40.0
+    sig = torch.rand(n_comp, 1, generator=gc, dtype=torch.float64) * 10.0
+    g = _gen(seed + 7919, device)
+    c = torch.randint(0, n_comp, (m,), generator=g, device=device)
+    z = torch.randn(m, d, generator=g, device=device, dtype=torch.float32)
+    X = centres.to(device=device, dtype=torch.float32)[c] + z * sig.to(device=device,
+                                                                        dtype=torch.float32)[c]
+    noise = (torch.rand(500, d, generator=g, device=device) * 2 - 1) * 50.0
+    X = torch.cat([X, noise]).contiguous()
+    comp = torch.cat([c, torch.full((500,), -1, dtype=c.dtype, device=device)])
+    return Mixture(X, comp, centres)
+
+
+def scaling_sample_size(m: int) -> int:
+    """s = min(5000, m - 1000) (Section 6.8)."""
+    return min(5000, m - 1000)

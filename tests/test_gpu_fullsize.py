@@ -193,3 +193,45 @@ def test_precision_set_bf16_full_size(hp, orc):
     assert cnt16.sum().item() == m
     _check_rows(orc, X, Cb, lab16, 200_000, seed=4)
     _say(f"precision: full assign SSE {sse16.item():.6e}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_metric_workload_full_size(hp, orc, tmp_path, prec):
+    """The benchmark's own configuration: m = 1e7, d = 32, k = 25, 1,024
+    workers x s = 10,000, autotuned plan, a cold round then a warm round
+    from the incumbents; sampled workers of both rounds against the oracle,
+    and the full assignment of the best incumbent on sampled rows."""
+    from paper_2311_04517_amd import tuning
+
+    mx = synthetic.metric_set(device="cuda")
+    X = mx.X
+    m, d = X.shape
+    W, s, k = 1024, 10_000, 25
+    desc, idx_len, c_len = hp.make_desc([s] * W, [k] * W, seed=1, sample_id=np.arange(W), d=d)
+    plan = hp.Plan(d, desc, idx_len, c_len, precision=prec)
+    idx = torch.empty(idx_len, dtype=torch.int64, device="cuda")
+    plan.draw(m, idx)
+    Ct = torch.full((c_len,), float("nan"), device="cuda")
+    plan.lloyd(X, idx, Ct)
+    tuning.tuned(plan, X, idx, Ct, path=str(tmp_path / "t.json"), max_iter=3)
+    del Ct
+    C = torch.empty(c_len, device="cuda")
+    C_inc = torch.full((c_len,), float("nan"), device="cuda")
+    f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device="cuda")
+    f_out = torch.empty(W, dtype=torch.float64, device="cuda")
+    it_out = torch.empty(W, dtype=torch.int32, device="cuda")
+    for r in range(2):
+        start = C_inc.cpu().numpy()
+        plan.round(X, idx, C, C_inc, f_inc, f_out, it_out)
+        torch.cuda.synchronize()
+        fg, itg, Cg = f_out.cpu().numpy(), it_out.cpu().numpy(), C.cpu().numpy()
+        _say(f"metric workload prec {prec} round {r}: passes {itg.sum()}")
+        assert ((itg >= 1) & (itg <= 300)).all() and np.isfinite(Cg).all()
+        rdesc, _, _ = hp.make_desc([s] * W, [k] * W, seed=1, sample_id=np.arange(W) + r * W, d=d)
+        nc = _check_samples(orc, X, idx, rdesc, [0, 511, 1023], start, Cg, fg, itg, d, m, 1)
+        assert nc >= 2
+    Cb, fb, wb = hp.select_best(C_inc.view(W, k, d), f_inc, k, d)
+    lab, cnt, sse = hp.assign_sse(X, Cb, precision=prec)
+    assert cnt.sum().item() == m
+    _check_rows(orc, X, Cb, lab, 200_000, seed=5)
+    plan.close()

@@ -426,3 +426,23 @@ def test_worker_loop_plain_small_config(hp, orc):
             assert_centroids(wg.C.cpu().numpy(), wo["C"], Xn)
             assert np.array_equal(wg.labels.cpu().numpy(), wo["labels"])
     assert e2e_ok >= 2
+
+
+def test_sizes_beyond_lds_are_refused(hp):
+    """k and padded d together must fit the workgroup's LDS: a combination
+    that does not (k = 512 at d = 128) is refused with HPC_ERR_UNSUPPORTED
+    before anything is launched, and the library stays usable."""
+    from paper_2311_04517_amd._lib import HPC_ERR_UNSUPPORTED, HpcError
+
+    Xg = torch.randn(4096, 128, device="cuda")
+    desc, idx_len, c_len = hp.make_desc([1024], [512], seed=0, sample_id=[0], d=128)
+    idx = hp.draw_samples(4096, desc, idx_len)
+    C = torch.full((c_len,), float("nan"), device="cuda")
+    with pytest.raises(HpcError) as e:
+        hp.lloyd_batch(Xg, idx, desc, C)
+    assert e.value.code == HPC_ERR_UNSUPPORTED
+    with pytest.raises(HpcError) as e:
+        hp.assign_sse(Xg, torch.randn(512, 128, device="cuda"))
+    assert e.value.code == HPC_ERR_UNSUPPORTED
+    lab, cnt, sse = hp.assign_sse(Xg, Xg[:8].contiguous())
+    assert cnt.sum().item() == 4096

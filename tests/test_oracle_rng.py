@@ -67,3 +67,19 @@ def test_sample_streams_independent_of_each_other(orc):
     assert np.array_equal(a, orc.draw_sample(10**9, 1000, 1, 0))
     # a prefix of a longer draw is the shorter draw
     assert np.array_equal(a[:333], orc.draw_sample(10**9, 333, 1, 0))
+
+
+def test_scaling_study_generator_shapes():
+    """Section 6.8: m = 3^(i+7) blob points in 10 dimensions plus 500 noise
+    points in (-50, 50); s = min(5000, m - 1000)."""
+    import synthetic
+
+    for i in (0, 1):
+        mx = synthetic.scaling_blobs(i, seed=2)
+        m = 3 ** (i + 7)
+        assert tuple(mx.X.shape) == (m + 500, 10)
+        assert (mx.comp[m:] == -1).all() and (mx.comp[:m] >= 0).all()
+        assert float(mx.X[m:].abs().max()) < 50.0
+        assert (mx.centres.abs() < 40).all()
+    assert synthetic.scaling_sample_size(3 ** 7) == 3 ** 7 - 1000
+    assert synthetic.scaling_sample_size(3 ** 15) == 5000
