@@ -28,6 +28,9 @@
 
 namespace hpc {
 
+// Passes a warm sample reads straight from X before it gathers its rows.
+constexpr int kDirectPasses = 6;
+
 struct LloydArgs {
     const float* X;
     int64_t m;
@@ -169,7 +172,10 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
                             uint64_t call, int32_t* __restrict__ chosen, Smem<D, NT, PREC>& L) {
     constexpr int NW = NT / kWave;
     constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
-    const int tid = threadIdx.x, wid = tid / kWave, lane = tid & 63;
+    // the wave index is wave-uniform: kept in scalar registers, and with it
+    // every LDS address derived from it
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid / kWave),
+              lane = tid & 63;
     const int g = lane >> 4, p = lane & 15;
     if (tid == 0) {
         int nd = 0, nv = 0;
@@ -183,7 +189,8 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
         L.ints[1] = nv;
     }
     __syncthreads();
-    const int n_deg = L.ints[0], n_valid = L.ints[1];
+    const int n_deg = __builtin_amdgcn_readfirstlane(L.ints[0]),
+              n_valid = __builtin_amdgcn_readfirstlane(L.ints[1]);
     if (n_deg == 0) return;
 
     const int cw = (((s + NW - 1) / NW) + 15) / 16 * 16;
@@ -375,7 +382,8 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
     constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
     S L(smem, a.kmax, a.n_copies);
     constexpr int NW = S::NW;
-    const int tid = threadIdx.x, wid = tid / kWave, lane = tid & 63;
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid / kWave),
+              lane = tid & 63;
     const int g = lane >> 4, pl = lane & 15;
     const int d = a.d;
     double alpha, beta;
@@ -384,7 +392,9 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
     for (;;) {
         if (tid == 0) L.ints[15] = atomicAdd(a.queue, 1);
         __syncthreads();
-        const int slot = L.ints[15];
+        // uniform across the workgroup: the sample's descriptor, sizes and
+        // base pointers then live in scalar registers
+        const int slot = __builtin_amdgcn_readfirstlane(L.ints[15]);
         __syncthreads();
         if (slot >= a.n_samples) break;
         const int b = a.order ? a.order[slot] : slot;
@@ -399,7 +409,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         // gather the sample rows (zero padded to D): consecutive threads
         // copy consecutive 16-byte chunks of a row; eight chunks per thread
         // are loaded before any is stored, so the random-row loads overlap
-        {
+        auto gather = [&]() {
             constexpr int NCH = D / 4;
             const int total = s * NCH;
             for (int base = tid; base < total; base += 8 * NT) {
@@ -432,12 +442,26 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 for (int u = 0; u < 8; ++u)
                     if (dst[u] >= 0) *reinterpret_cast<float4*>(Sg + dst[u]) = v[u];
             }
-        }
+            __syncthreads();
+        };
         for (int e = tid; e < k * CS; e += NT) {
             const int j = e / CS, t = e % CS;
             L.C64[e] = t < d ? (double)a.C[ds.c_offset + (int64_t)j * d + t] : 0.0;
         }
         __syncthreads();
+        // a sample that starts with every centroid valid is read straight
+        // from X through its indices (rows of exactly D floats, 16-byte
+        // aligned); the gathered copy is made when K-means++ needs the
+        // sample (a degenerate row at the start or after an update) or when
+        // the sample runs long
+        auto any_degenerate = [&]() {
+            int deg = 0;
+            for (int j = tid; j < k; j += NT) deg |= L.C64[j * CS] != L.C64[j * CS];
+            return __syncthreads_or(deg) != 0;
+        };
+        const bool direct_ok = !a.seed_only && a.vec4 && d == D;
+        bool gathered = !direct_ok || any_degenerate();
+        if (gathered) gather();
 
         if (a.seed_only) {
             if (a.chosen)
@@ -453,6 +477,15 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             float qscale;
             key_params(nblk, &kmask, &qscale);
             for (;;) {
+                // reading rows through the indices costs more per pass than
+                // reading the gathered copy (scattered 128-byte rows against
+                // contiguous ones; about a seventh of the copy's cost): a
+                // sample still running after kDirectPasses passes makes the
+                // copy, which bounds the loss to twice the better choice
+                if (!gathered && it > 0 && (it >= kDirectPasses || any_degenerate())) {
+                    gather();
+                    gathered = true;
+                }
                 kmeanspp_wg<D, NT, PREC>(sv, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
                                          (uint64_t)it, nullptr, L);
                 const double cmax = centroid_max_norm<D, NT, PREC>(L, k, d);
@@ -526,17 +559,52 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         if (g == 0 && a.labels_out) a.labels_out[ds.idx_offset + i] = am;
                     }
                 };
-                fetch(wid, xa, la);
-                fetch(wid + NW, xb, lb);
-                for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
-                    fetch(tile + 2 * NW, xc, lc);
-                    process(tile, xa, la);
-                    if ((tile + NW) * 16 >= s) break;
-                    fetch(tile + 3 * NW, xa, la);
-                    process(tile + NW, xb, lb);
-                    if ((tile + 2 * NW) * 16 >= s) break;
-                    fetch(tile + 4 * NW, xb, lb);
-                    process(tile + 2 * NW, xc, lc);
+                if (gathered) {
+                    fetch(wid, xa, la);
+                    fetch(wid + NW, xb, lb);
+                    for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
+                        fetch(tile + 2 * NW, xc, lc);
+                        process(tile, xa, la);
+                        if ((tile + NW) * 16 >= s) break;
+                        fetch(tile + 3 * NW, xa, la);
+                        process(tile + NW, xb, lb);
+                        if ((tile + 2 * NW) * 16 >= s) break;
+                        fetch(tile + 4 * NW, xb, lb);
+                        process(tile + 2 * NW, xc, lc);
+                    }
+                } else {
+                    // rows straight from X: each tile's indices are loaded
+                    // two tiles before its rows, so a row load never waits
+                    // on rows still in flight
+                    const int64_t* ix = a.idx + ds.idx_offset;
+                    auto IDX = [&](int tile) -> int64_t { return ix[min(tile * 16 + pl, s - 1)]; };
+                    // an index outside [0, m) reads row 0 and is zeroed,
+                    // as the gather does
+                    auto ROW = [&](int tile, int64_t r, float (&dst)[DL], int& old) {
+                        const bool in_range = r >= 0 && r < a.m;
+                        load_quarter<D>(a.X + (in_range ? r : 0) * D, g, dst);
+#pragma unroll
+                        for (int t = 0; t < DL; ++t) dst[t] = in_range ? dst[t] : 0.f;
+                        old = lprev[min(tile * 16 + pl, s - 1)];
+                    };
+                    int64_t ia = IDX(wid), ib = IDX(wid + NW), ic = IDX(wid + 2 * NW);
+                    ROW(wid, ia, xa, la);
+                    ROW(wid + NW, ib, xb, lb);
+                    ia = IDX(wid + 3 * NW);
+                    ib = IDX(wid + 4 * NW);
+                    for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
+                        ROW(tile + 2 * NW, ic, xc, lc);
+                        ic = IDX(tile + 5 * NW);
+                        process(tile, xa, la);
+                        if ((tile + NW) * 16 >= s) break;
+                        ROW(tile + 3 * NW, ia, xa, la);
+                        ia = IDX(tile + 6 * NW);
+                        process(tile + NW, xb, lb);
+                        if ((tile + 2 * NW) * 16 >= s) break;
+                        ROW(tile + 4 * NW, ib, xb, lb);
+                        ib = IDX(tile + 7 * NW);
+                        process(tile + 2 * NW, xc, lc);
+                    }
                 }
                 f = block_sum<NT>(fl, L.red);
                 ++it;

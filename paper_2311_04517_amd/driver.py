@@ -195,3 +195,91 @@ def run_budget(X, *, W: int, s: int, k: int, seed: int, T: float, strategy: str 
     if log.n_dist:
         log.n_dist[-1] += m * k
     return log
+
+
+@dataclass
+class StreamResult:
+    state: StrategyState
+    f_rounds: list         # per round: f of every worker (host float64 arrays)
+    iters_rounds: list     # per round: passes of every worker
+    t_rounds: list         # per round: end time in seconds from the start (HIP events)
+
+
+def run_stream(source, *, W: int, s: int, k: int, d: int, seed: int, n_rounds: int,
+               strategy: str = "competitive", n_competitive: int = 0, max_iter=300,
+               rel_tol=1e-4, precision=api.PREC_FP32):
+    """HPClust on a stream of data (the infinitely tall setting of Section 1,
+    m = infinity; streaming sources are the paper's stated future direction):
+    round r's samples are the next W*s points of the stream, source(r)
+    returning them as a host float32 array of shape (W*s, d), worker w taking
+    rows [w*s, (w+1)*s).  Blocks are staged in pinned host memory and copied
+    to the device on a second stream while the previous round's kernels run
+    (two buffers; events order each round after its copy and each copy after
+    the round that last read its buffer).  Incumbents and strategies are as
+    in strategy_round; sample ids are r*W + w."""
+    import numpy as np
+
+    if strategy not in ("competitive", "cooperative", "hybrid"):
+        raise ValueError(strategy)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    n = W * s
+    pinned = [torch.empty((n, d), dtype=torch.float32, pin_memory=True) for _ in range(2)]
+    bufs = [torch.empty((n, d), dtype=torch.float32, device=dev) for _ in range(2)]
+    copied = [torch.cuda.Event() for _ in range(2)]
+    used = [torch.cuda.Event() for _ in range(2)]
+    staged = [None, None]  # copy-stream events guarding the pinned buffers
+    compute = torch.cuda.current_stream()
+    copy_stream = torch.cuda.Stream()
+    idx = torch.arange(n, dtype=torch.int64, device=dev)
+    state = new_state(W, k, d, dev)
+    C = torch.empty_like(state.C_inc)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t0.record(compute)
+    ends = []
+    out_f, out_it = [], []
+
+    def stage(r):
+        b = r % 2
+        if staged[b] is not None:
+            staged[b].synchronize()  # the previous copy out of this pinned buffer is done
+        block = np.asarray(source(r), dtype=np.float32)
+        if block.shape != (n, d):
+            raise ValueError(f"source({r}) returned shape {block.shape}, expected {(n, d)}")
+        pinned[b].numpy()[...] = block
+        with torch.cuda.stream(copy_stream):
+            copy_stream.wait_event(used[b])  # the round that last read bufs[b] has finished
+            bufs[b].copy_(pinned[b], non_blocking=True)
+            copied[b].record(copy_stream)
+        staged[b] = torch.cuda.Event()
+        staged[b].record(copy_stream)
+
+    for b in range(2):
+        used[b].record(compute)
+    stage(0)
+    for r in range(n_rounds):
+        b = r % 2
+        coop = strategy == "cooperative" or (strategy == "hybrid" and r >= n_competitive)
+        compute.wait_event(copied[b])
+        if coop:
+            Cb, _, _ = api.select_best(state.C_inc, state.f_inc, k, d)
+            C.copy_(Cb.unsqueeze(0).expand(W, k, d))
+        else:
+            C.copy_(state.C_inc)
+        desc, _, _ = api.make_desc([s] * W, [k] * W, seed=seed,
+                                   sample_id=[r * W + w for w in range(W)], d=d)
+        f, it, _ = api.lloyd_batch(bufs[b], idx, desc, C, max_iter=max_iter, rel_tol=rel_tol,
+                                   precision=precision)
+        api.keep_best(C, f, state.C_inc, state.f_inc, k, d)
+        used[b].record(compute)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(compute)
+        ends.append(e)
+        out_f.append(f)
+        out_it.append(it)
+        state.round += 1
+        if r + 1 < n_rounds:
+            stage(r + 1)  # host fill and copy overlap this round's kernels
+    torch.cuda.synchronize()
+    return StreamResult(state, [f.cpu().numpy() for f in out_f],
+                        [i.cpu().numpy() for i in out_it],
+                        [t0.elapsed_time(e) / 1e3 for e in ends])
