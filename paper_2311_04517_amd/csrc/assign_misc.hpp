@@ -121,8 +121,9 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
         const int64_t i = tile * 16 + (lane & 15);
         const bool valid = i < m;
         const float xn2 = point_norm2<D>(xq);
-        const Top3 t3 = screen_tile<D, PREC>(xq, aop, nrm, nblk, xn2, kmask);
         const float xn = cert_norm(xn2);
+        const Top3 t3 =
+            screen_tile<D, PREC>(xq, aop, nrm, nblk, screen_shift(xn2, xn, ea, eb), kmask);
         const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
         const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
         int am = redecide64<D>(xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb),

@@ -124,6 +124,14 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 __device__ __forceinline__ bool is_nan_f(float v) { return v != v; }
 
+// FP64 data in LDS addressed as such (32-bit addresses; a generic pointer
+// into LDS keeps 64-bit address arithmetic), and its atomic add.
+typedef __attribute__((address_space(3))) double lds_f64;
+__device__ __forceinline__ lds_f64* as_lds(double* p) { return (lds_f64*)p; }
+__device__ __forceinline__ void lds_add(lds_f64* p, double v) {
+    __builtin_amdgcn_ds_atomic_fadd_f64(p, v);
+}
+
 // ---------------------------------------------------------------------------
 // Exchange with lane l ^ 16 / l ^ 32 through the gfx950 row-swap
 // instructions (VALU, no LDS round trip).  v_permlane16_swap(a, a) leaves,
@@ -146,6 +154,41 @@ __device__ __forceinline__ float lane_xor(float v, int o) {
 __device__ __forceinline__ int lane_xor(int v, int o) {
     const unsigned u = (unsigned)v;
     return (int)(o == 16 ? xor16_u32(u) : xor32_u32(u));
+}
+// Both values of the lane pair {l, l ^ 16} (O = 16) or {l, l ^ 32} (O = 32),
+// the lower lane's first, identical in the two lanes of the pair: in the
+// swap of v with itself the first result keeps the lower row's value and
+// the second the upper row's.  A combination of the two is therefore the
+// same in both lanes without a per-lane select.
+template <int O>
+__device__ __forceinline__ void lane_pair(unsigned v, unsigned& lo, unsigned& hi) {
+    static_assert(O == 16 || O == 32, "pair distance");
+    if constexpr (O == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        lo = r[0];
+        hi = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        lo = r[0];
+        hi = r[1];
+    }
+}
+// Sum over the lane pair (same value, same rounding, in both lanes).
+template <int O>
+__device__ __forceinline__ float pair_sum(float v) {
+    unsigned lo, hi;
+    lane_pair<O>(__float_as_uint(v), lo, hi);
+    return __uint_as_float(lo) + __uint_as_float(hi);
+}
+template <int O>
+__device__ __forceinline__ double pair_sum(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    unsigned l0, h0, l1, h1;
+    lane_pair<O>((unsigned)u, l0, h0);
+    lane_pair<O>((unsigned)(u >> 32), l1, h1);
+    const double lo = __longlong_as_double((long long)(((unsigned long long)l1 << 32) | l0));
+    const double hi = __longlong_as_double((long long)(((unsigned long long)h1 << 32) | h0));
+    return lo + hi;
 }
 __device__ __forceinline__ double lane_xor(double v, int o) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);

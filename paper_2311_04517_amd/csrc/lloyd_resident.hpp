@@ -31,6 +31,10 @@ namespace hpc {
 // Passes a warm sample reads straight from X before it gathers its rows.
 constexpr int kDirectPasses = 6;
 
+// A row of zeros in global memory, read in place of a row whose index lies
+// outside [0, m) (never written).
+__device__ float g_zero_row[128];
+
 struct LloydArgs {
     const float* X;
     int64_t m;
@@ -74,8 +78,8 @@ struct Smem {
     void* aop;     // MFMA A operands, nblk x ... (see mfma_screen.hpp)
     float* nrm;    // nblk*16 score biases |c|^2
     double* crow;  // 4 x D candidate rows
-    double* psum;  // n_copies x kmax rows (stride CS) of running update sums
-    int* pcnt;     // n_copies x kmax counts
+    double* psum;  // n_copies x kmax rows (stride CS) of running update sums;
+                   // slot D of a row (the stride's padding) holds the count
     double* red;   // 4 x NW wave partials
     double* cn;    // kmax squared centroid norms
     int* deg;      // kmax degenerate-row list
@@ -85,7 +89,7 @@ struct Smem {
     static __host__ __device__ int nblk_of(int kmax) { return (kmax + 15) / 16; }
 
     static __host__ __device__ size_t union_bytes(int kmax, int copies) {
-        return (size_t)copies * kmax * Lay<D>::CS * 8 + align_up((size_t)copies * kmax * 4, 16);
+        return (size_t)copies * kmax * Lay<D>::CS * 8;
     }
     static __host__ __device__ size_t bytes(int kmax, int copies) {
         const int nb = nblk_of(kmax);
@@ -109,7 +113,6 @@ struct Smem {
         crow = reinterpret_cast<double*>(p);
         p += 4 * D * 8;
         psum = reinterpret_cast<double*>(p);
-        pcnt = reinterpret_cast<int*>(p + (size_t)copies * kmax * Lay<D>::CS * 8);
         p += union_bytes(kmax, copies);
         red = reinterpret_cast<double*>(p);
         p += 4 * NW * 8;
@@ -404,6 +407,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         float* Sg = a.sbuf + (size_t)ds.idx_offset * D;
         double* d2 = a.d2buf + ds.idx_offset;
         int32_t* lprev = a.lbuf + ds.idx_offset;
+        int32_t* lab_out = a.labels_out ? a.labels_out + ds.idx_offset : nullptr;
         const SampleView<D> sv{Sg};
 
         // gather the sample rows (zero padded to D): consecutive threads
@@ -494,13 +498,10 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // the sums and counts run across passes: the first pass adds
                 // every point, later passes only the points whose label changed
                 const bool first = it == 0;
-                if (first) {
+                if (first)
                     for (int e = tid; e < copies * k * CS; e += NT) L.psum[e] = 0.0;
-                    for (int e = tid; e < copies * k; e += NT) L.pcnt[e] = 0;
-                }
                 __syncthreads();
-                double* pw = L.psum + (size_t)(wid % copies) * k * CS;
-                int* cw = L.pcnt + (wid % copies) * k;
+                lds_f64* pw = as_lds(L.psum + (size_t)(wid % copies) * k * CS);
                 double fl = 0.0;
                 // tiles of 16 points per wave, software pipelined over three
                 // register buffers: the rows of the next two tiles are in
@@ -514,14 +515,15 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 auto fetch = [&](int tile, float (&dst)[DL], int& old) {
                     const int i = min(tile * 16 + pl, s - 1);
                     load_quarter<D>(Sg + (size_t)i * D, g, dst);
-                    old = lprev[i];
+                    old = lprev[(unsigned)i];
                 };
                 auto process = [&](int tile, const float (&xq)[DL], int old) {
                     const int i = tile * 16 + pl;
                     const bool valid = i < s;
                     const float xn2 = point_norm2<D>(xq);
-                    const Top3 t3 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk, xn2, kmask);
                     const float xn = cert_norm(xn2);
+                    const Top3 t3 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk,
+                                                         screen_shift(xn2, xn, ea, eb), kmask);
                     const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
                     const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
                     const int am = redecide64<D>(
@@ -542,21 +544,22 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         fl += part;
                         const int prev = first ? -1 : old;
                         if (am != prev) {
-                            double* pn = pw + am * CS + g * DL;
+                            lds_f64* pn = pw + (am * CS + g * DL);
 #pragma unroll
-                            for (int t = 0; t < DL; ++t) atomicAdd(pn + t, (double)xq[t]);
+                            for (int t = 0; t < DL; ++t) lds_add(pn + t, (double)xq[t]);
                             if (prev >= 0) {
-                                double* po = pw + prev * CS + g * DL;
+                                lds_f64* po = pn + (prev - am) * CS;
 #pragma unroll
-                                for (int t = 0; t < DL; ++t) atomicAdd(po + t, -(double)xq[t]);
+                                for (int t = 0; t < DL; ++t) lds_add(po + t, -(double)xq[t]);
                             }
                             if (g == 0) {
-                                atomicAdd(cw + am, 1);
-                                if (prev >= 0) atomicAdd(cw + prev, -1);
-                                lprev[i] = am;
+                                // counts are small integers, exact in FP64
+                                lds_add(pw + (am * CS + D), 1.0);
+                                if (prev >= 0) lds_add(pw + (prev * CS + D), -1.0);
+                                lprev[(unsigned)i] = am;
                             }
                         }
-                        if (g == 0 && a.labels_out) a.labels_out[ds.idx_offset + i] = am;
+                        if (g == 0 && lab_out) lab_out[(unsigned)i] = am;
                     }
                 };
                 if (gathered) {
@@ -577,33 +580,42 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     // two tiles before its rows, so a row load never waits
                     // on rows still in flight
                     const int64_t* ix = a.idx + ds.idx_offset;
-                    auto IDX = [&](int tile) -> int64_t { return ix[min(tile * 16 + pl, s - 1)]; };
-                    // an index outside [0, m) reads row 0 and is zeroed,
-                    // as the gather does
-                    auto ROW = [&](int tile, int64_t r, float (&dst)[DL], int& old) {
-                        const bool in_range = r >= 0 && r < a.m;
-                        load_quarter<D>(a.X + (in_range ? r : 0) * D, g, dst);
-#pragma unroll
-                        for (int t = 0; t < DL; ++t) dst[t] = in_range ? dst[t] : 0.f;
-                        old = lprev[min(tile * 16 + pl, s - 1)];
+                    auto IDX = [&](int tile) -> int64_t {
+                        return ix[(unsigned)min(tile * 16 + pl, s - 1)];
                     };
+                    // an index outside [0, m) reads a row of zeros, as the
+                    // gather does (a pointer select: nothing touches the
+                    // loaded registers before they are used)
+                    auto ROW = [&](int tile, int64_t r, float (&dst)[DL], int& old) {
+                        const float* src = (r >= 0 && r < a.m) ? a.X + r * D : g_zero_row;
+                        load_quarter<D>(src, g, dst);
+                        old = lprev[(unsigned)min(tile * 16 + pl, s - 1)];
+                    };
+                    // the prologue issues its loads in the order the loop
+                    // body does (the scheduling barriers stop the compiler
+                    // from sinking the third tile's indices, which would make
+                    // the loop head wait for every load in flight)
                     int64_t ia = IDX(wid), ib = IDX(wid + NW), ic = IDX(wid + 2 * NW);
+                    __builtin_amdgcn_sched_barrier(0);
                     ROW(wid, ia, xa, la);
+                    __builtin_amdgcn_sched_barrier(0);
                     ROW(wid + NW, ib, xb, lb);
+                    __builtin_amdgcn_sched_barrier(0);
                     ia = IDX(wid + 3 * NW);
                     ib = IDX(wid + 4 * NW);
+                    __builtin_amdgcn_sched_barrier(0);
+                    // no early exit inside the body (the loads past the end
+                    // are clamped and cheap; skipped tiles are not processed)
                     for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
                         ROW(tile + 2 * NW, ic, xc, lc);
                         ic = IDX(tile + 5 * NW);
                         process(tile, xa, la);
-                        if ((tile + NW) * 16 >= s) break;
                         ROW(tile + 3 * NW, ia, xa, la);
                         ia = IDX(tile + 6 * NW);
-                        process(tile + NW, xb, lb);
-                        if ((tile + 2 * NW) * 16 >= s) break;
+                        if ((tile + NW) * 16 < s) process(tile + NW, xb, lb);
                         ROW(tile + 4 * NW, ib, xb, lb);
                         ib = IDX(tile + 7 * NW);
-                        process(tile + 2 * NW, xc, lc);
+                        if ((tile + 2 * NW) * 16 < s) process(tile + 2 * NW, xc, lc);
                     }
                 }
                 f = block_sum<NT>(fl, L.red);
@@ -612,14 +624,13 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 f_prev = f;
                 for (int e = tid; e < k * CS; e += NT) {
                     const int j = e / CS, t = e % CS;
-                    double sum = 0.0;
-                    int n = 0;
+                    double sum = 0.0, n = 0.0;
                     for (int gg = 0; gg < copies; ++gg) {
                         sum += L.psum[(size_t)gg * k * CS + e];
-                        n += L.pcnt[gg * k + j];
+                        n += L.psum[(size_t)gg * k * CS + j * CS + D];
                     }
                     double v = 0.0;
-                    if (t < d) v = n > 0 ? sum / (double)n : __builtin_nan("");
+                    if (t < d) v = n > 0.0 ? sum / n : __builtin_nan("");
                     L.C64[e] = v;
                 }
                 __syncthreads();

@@ -17,13 +17,15 @@
 // four lanes of a point merge their three best with two XOR exchanges.
 //
 // Keys.  Each screened score becomes the distance estimate v_j = fl(s~_j +
-// |x|~^2) (|x|~^2 the FP32 norm of the point, the same for every j),
-// clamped at +0, and its NB low mantissa bits are replaced by j
-// (2^NB >= padded k).  For non-negative floats the bit patterns order like
-// the values, so the three smallest keys -- found with integer min/max
-// only -- are the three smallest quantised estimates with their indices.
-// Padding rows (score +inf) give keys at or above 0x7F800000, above every
-// finite key.
+// h) with h = fl(|x|~^2 + b): |x|~^2 is the FP32 norm of the point and b =
+// 1.25 E(x) + 2^-16 |x|~^2 bounds the screening error (below) and the
+// norm's rounding (under 2^-18 |x|^2 for d <= 128), so that v_j >= +0
+// without a clamp; h is the same for every j of the point.  The NB low
+// mantissa bits of v_j are replaced by j (2^NB >= padded k).  For
+// non-negative floats the bit patterns order like the values, so the three
+// smallest keys -- found with integer min/max only -- are the three
+// smallest quantised estimates with their indices.  Padding rows (score
+// +inf) give keys at or above 0x7F800000, above every finite key.
 //
 // Certificate.  Let E(x) bound |s~_j - s_j| for the screened score, s_j the
 // exact score of the FP64 centroid; E(x) = alpha |x| cmax + beta cmax^2 with
@@ -34,8 +36,9 @@
 // classical accumulation bound of d + 1 FP32 additions (the factor two
 // leaves room for the matrix unit's internal summation order), plus the
 // rounding of |c|^2 to FP32.  The quantised key value q_j satisfies
-// q_j <= max(v_j, 0) < q_j (1 + 2^(NB-23)) + 0, and fl() adds a relative
-// 2^-24; the common error of |x|~^2 cancels between j.  Hence with q_1 <=
+// q_j <= v_j < q_j (1 + 2^(NB-23)), and fl() adds a relative 2^-24; h,
+// common to all j, cancels between them (its share of q_j only enlarges
+// the right-hand side of the test below).  Hence with q_1 <=
 // q_2 the two best keys, every j other than the winner has s_j > s_winner
 // whenever  q_2 - q_1 > 2E + 2^(NB-22) q_1 + 2^-23 (q_1 + q_2),  and the
 // test below uses the stronger  q_2 - q_1 > 2.5 E + 2^(NB-20) q_2  (the
@@ -148,11 +151,16 @@ struct Top3 {
     unsigned t1, t2, t3;
 };
 
-// Key of centroid j: max(v, +0) with the low bits under `kmask` set to j.
+// Key of centroid j: v (non-negative, see screen_shift) with the low bits
+// under `kmask` set to j.
 __device__ __forceinline__ unsigned screen_key(float v, unsigned kmask, unsigned j) {
-    const int bits = __float_as_int(v);
-    const unsigned pos = (unsigned)(bits > 0 ? bits : 0);  // negatives and -0 to +0
-    return (pos & ~kmask) | j;
+    return (__float_as_uint(v) & ~kmask) | j;
+}
+
+// h = |x|~^2 + 1.25 E(x) + 2^-16 |x|~^2 (see Keys above): every distance
+// estimate fl(s~_j + h) is >= +0.  ea, eb as in certified().
+__device__ __forceinline__ float screen_shift(float xn2, float xnorm, float ea, float eb) {
+    return xn2 + (1.25f * __fmaf_rn(ea, xnorm, eb) + 0x1.0p-16f * xn2);
 }
 
 // Median of three (one v_med3_u32).
@@ -170,18 +178,28 @@ __device__ __forceinline__ void top3_insert(Top3& t, unsigned key) {
     t.t3 = n3;
 }
 
-// Merge with the lane at XOR distance o (the lanes hold disjoint centroid
-// sets, so keys are distinct and both lanes end with the same triple).  The
-// other triple is ascending: its second key ranks second at best, its third
-// third at best.
-__device__ __forceinline__ void top3_merge(Top3& t, int o) {
-    const unsigned o1 = (unsigned)lane_xor((int)t.t1, o);
-    const unsigned o2 = (unsigned)lane_xor((int)t.t2, o);
-    const unsigned o3 = (unsigned)lane_xor((int)t.t3, o);
-    top3_insert(t, o1);
-    const unsigned n3 = umed3(t.t2, t.t3, o2);
-    t.t2 = min(t.t2, o2);
-    t.t3 = min(n3, o3);
+// The three smallest of two ascending triples a and b: the r-th smallest of
+// their union is the minimum over i + j = r of max(a_i, b_j) (a_0 = b_0 =
+// -inf), i.e. min(a1, b1); min(a2, b2, max(a1, b1)); min(a3, b3, max(a2,
+// b1), max(a1, b2)).
+__device__ __forceinline__ Top3 top3_union(const Top3& a, const Top3& b) {
+    Top3 t;
+    t.t1 = min(a.t1, b.t1);
+    t.t2 = min(min(a.t2, b.t2), max(a.t1, b.t1));
+    t.t3 = min(min(min(a.t3, b.t3), max(a.t2, b.t1)), max(a.t1, b.t2));
+    return t;
+}
+
+// Merge with the lane at XOR distance O: both lanes combine the same two
+// triples (the lower lane's and the upper lane's), so they end with the
+// same result.
+template <int O>
+__device__ __forceinline__ void top3_merge(Top3& t) {
+    Top3 lo, hi;
+    lane_pair<O>(t.t1, lo.t1, hi.t1);
+    lane_pair<O>(t.t2, lo.t2, hi.t2);
+    lane_pair<O>(t.t3, lo.t3, hi.t3);
+    t = top3_union(lo, hi);
 }
 
 __device__ __forceinline__ unsigned key_index(unsigned key, unsigned kmask) { return key & kmask; }
@@ -199,12 +217,12 @@ __device__ __forceinline__ void key_params(int nblk, unsigned* kmask, float* qsc
 }
 
 // Keys of this lane's point against all nblk*16 centroids; returns the
-// merged three best (identical in the point's four lanes).  xn2: the
-// point's FP32 |x|^2.
+// merged three best (identical in the point's four lanes).  h: the point's
+// shifted norm from screen_shift.
 template <int D, int PREC>
 __device__ __forceinline__ Top3 screen_tile(const float (&xq)[Lay<D>::DL],
                                             const void* __restrict__ aop,
-                                            const float* __restrict__ nrm, int nblk, float xn2,
+                                            const float* __restrict__ nrm, int nblk, float h,
                                             unsigned kmask) {
     constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
     const int lane = threadIdx.x & 63, g = lane >> 4;
@@ -219,7 +237,7 @@ __device__ __forceinline__ Top3 screen_tile(const float (&xq)[Lay<D>::DL],
                                                            acc, 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                top3_insert(t, screen_key(acc[r] + xn2, kmask, (unsigned)(blk * 16 + 4 * g + r)));
+                top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
         }
     } else {
         bf16x8 xb[KC];
@@ -239,24 +257,22 @@ __device__ __forceinline__ Top3 screen_tile(const float (&xq)[Lay<D>::DL],
                                                               acc, 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                top3_insert(t, screen_key(acc[r] + xn2, kmask, (unsigned)(blk * 16 + 4 * g + r)));
+                top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
         }
     }
-    top3_merge(t, 16);
-    top3_merge(t, 32);
+    top3_merge<16>(t);
+    top3_merge<32>(t);
     return t;
 }
 
-// |x|^2 of this lane's point (same value in its four lanes).  Used only by
-// the certificate, whose 2.5 factor covers its rounding.
+// |x|^2 of this lane's point (same value in its four lanes).  Used by the
+// key shift and the certificate, whose factors cover its rounding.
 template <int D>
 __device__ __forceinline__ float point_norm2(const float (&xq)[Lay<D>::DL]) {
     float s = 0.f;
 #pragma unroll
     for (int t = 0; t < Lay<D>::DL; ++t) s = __fmaf_rn(xq[t], xq[t], s);
-    s += lane_xor(s, 16);
-    s += lane_xor(s, 32);
-    return s;
+    return pair_sum<32>(pair_sum<16>(s));
 }
 
 // FP64 |x - c|^2 of this lane's point to the FP64 centroid row c,
@@ -272,9 +288,7 @@ __device__ __forceinline__ double quarter_dist64(const float (&xq)[Lay<D>::DL],
         const double e = (double)xq[t] - c[g * DL + t];
         p = __fma_rn(e, e, p);
     }
-    p += lane_xor(p, 16);
-    p += lane_xor(p, 32);
-    return p;
+    return pair_sum<32>(pair_sum<16>(p));
 }
 
 // |x| for the certificate: hardware square root (within 1 ulp), the 2.5
