@@ -36,7 +36,7 @@
  *  - Supported sizes: 1 <= d <= 128, 1 <= k <= 512, k <= s, m < 2^62, and
  *    the k centroids (FP64, with the per-cluster sums for Lloyd) must fit a
  *    workgroup's 160 KiB of LDS.  Largest k per padded d (8, 16, 32, 64,
- *    128) for Lloyd: 512, 463, 240, 121, 60 (FP32 screening), 512, 463, 266,
+ *    128) for Lloyd: 512, 462, 240, 121, 60 (FP32 screening), 512, 462, 266,
  *    135, 66 (BF16); for hpc_assign_sse: 512, 512, 400, 207, 101 (FP32),
  *    512, 512, 480, 246, 125 (BF16).  Larger combinations are refused with
  *    HPC_ERR_UNSUPPORTED before anything is launched.

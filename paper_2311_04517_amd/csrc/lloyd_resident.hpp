@@ -31,6 +31,11 @@ namespace hpc {
 // Passes a warm sample reads straight from X before it gathers its rows.
 constexpr int kDirectPasses = 6;
 
+// Smallest objective, relative to the sample's scatter Q about its
+// reference point, that is taken from the running sums (below it the
+// points are summed directly; see the pass loop).
+constexpr double kSumsObjectiveMin = 1e-2;
+
 // A row of zeros in global memory, read in place of a row whose index lies
 // outside [0, m) (never written).
 __device__ float g_zero_row[128];
@@ -78,8 +83,10 @@ struct Smem {
     void* aop;     // MFMA A operands, nblk x ... (see mfma_screen.hpp)
     float* nrm;    // nblk*16 score biases |c|^2
     double* crow;  // 4 x D candidate rows
-    double* psum;  // n_copies x kmax rows (stride CS) of running update sums;
-                   // slot D of a row (the stride's padding) holds the count
+    double* ref;   // D coordinates of the sample's reference point r
+    double* psum;  // n_copies x kmax rows (stride CS) of running update sums
+                   // of x - r; slot D of a row (the stride's padding) holds
+                   // the count
     double* red;   // 4 x NW wave partials
     double* cn;    // kmax squared centroid norms
     int* deg;      // kmax degenerate-row list
@@ -95,7 +102,7 @@ struct Smem {
         const int nb = nblk_of(kmax);
         size_t b = align_up((size_t)kmax * Lay<D>::CS * 8, 16) + align_up(aop_bytes<D, PREC>(nb), 16) +
                    (size_t)nb * 64;
-        b += 4 * D * 8;
+        b += 4 * D * 8 + D * 8;
         b += union_bytes(kmax, copies);
         b += 4 * NW * 8 + align_up((size_t)kmax * 8, 16);
         b += align_up((size_t)kmax * 4, 16) + 16 * 4;
@@ -112,6 +119,8 @@ struct Smem {
         p += (size_t)nb * 64;
         crow = reinterpret_cast<double*>(p);
         p += 4 * D * 8;
+        ref = reinterpret_cast<double*>(p);
+        p += D * 8;
         psum = reinterpret_cast<double*>(p);
         p += union_bytes(kmax, copies);
         red = reinterpret_cast<double*>(p);
@@ -474,7 +483,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             kmeanspp_wg<D, NT, PREC>(sv, s, k, a.n_cand, d2, ds.seed, kTagSeed, ds.sample_id,
                                      a.call_id, a.chosen, L);
         } else {
-            double f_prev = __builtin_huge_val(), f = 0.0;
+            double f_prev = __builtin_huge_val(), f = 0.0, Qr = 0.0;
             int it = 0;
             const int copies = a.n_copies;
             unsigned kmask;
@@ -496,10 +505,25 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
                 build_operands<D, PREC, NT>(L.C64, k, d, nblk, L.aop, L.nrm);
                 // the sums and counts run across passes: the first pass adds
-                // every point, later passes only the points whose label changed
+                // every point, later passes only the points whose label
+                // changed.  They are sums of x - r for a reference point r
+                // fixed per sample (the mean of the first pass's centroids,
+                // rounded to FP32 so that x - r is exact in FP64), which keeps
+                // them and the objective below free of cancellation.
                 const bool first = it == 0;
-                if (first)
+                if (first) {
                     for (int e = tid; e < copies * k * CS; e += NT) L.psum[e] = 0.0;
+                    for (int t = tid; t < D; t += NT) {
+                        double sum = 0.0;
+                        int nv = 0;
+                        for (int j = 0; j < k; ++j)
+                            if (L.C64[j * CS] == L.C64[j * CS]) {
+                                sum += L.C64[j * CS + t];
+                                ++nv;
+                            }
+                        L.ref[t] = t < d && nv > 0 ? (double)(float)(sum / nv) : 0.0;
+                    }
+                }
                 __syncthreads();
                 lds_f64* pw = as_lds(L.psum + (size_t)(wid % copies) * k * CS);
                 double fl = 0.0;
@@ -530,27 +554,30 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb), a1,
                         a2 < k ? a2 : a1, L.C64, k);
                     if (valid) {
-                        // this lane's share of the objective; a point that
-                        // changed cluster moves its coordinates between the
-                        // running sums (padded coordinates are zero in the
-                        // gathered rows, so their sums stay exactly zero)
-                        const double* cr = L.C64 + am * CS + g * DL;
-                        double part = 0.0;
-#pragma unroll
-                        for (int t = 0; t < DL; ++t) {
-                            const double e = (double)xq[t] - cr[t];
-                            part = __fma_rn(e, e, part);
-                        }
-                        fl += part;
+                        // a point that changed cluster moves x - r between the
+                        // running sums (padded coordinates of x and r are
+                        // zero, so their sums stay exactly zero); in the first
+                        // pass every point does, and adds its share of
+                        // Q = sum |x - r|^2
                         const int prev = first ? -1 : old;
                         if (am != prev) {
+                            const double* rq = L.ref + g * DL;
+                            double xr[DL];
+#pragma unroll
+                            for (int t = 0; t < DL; ++t) xr[t] = (double)xq[t] - rq[t];
+                            if (first) {
+                                double part = 0.0;
+#pragma unroll
+                                for (int t = 0; t < DL; ++t) part = __fma_rn(xr[t], xr[t], part);
+                                fl += part;
+                            }
                             lds_f64* pn = pw + (am * CS + g * DL);
 #pragma unroll
-                            for (int t = 0; t < DL; ++t) lds_add(pn + t, (double)xq[t]);
+                            for (int t = 0; t < DL; ++t) lds_add(pn + t, xr[t]);
                             if (prev >= 0) {
                                 lds_f64* po = pn + (prev - am) * CS;
 #pragma unroll
-                                for (int t = 0; t < DL; ++t) lds_add(po + t, -(double)xq[t]);
+                                for (int t = 0; t < DL; ++t) lds_add(po + t, -xr[t]);
                             }
                             if (g == 0) {
                                 // counts are small integers, exact in FP64
@@ -618,7 +645,56 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         if ((tile + 2 * NW) * 16 < s) process(tile + 2 * NW, xc, lc);
                     }
                 }
-                f = block_sum<NT>(fl, L.red);
+                // The pass objective from the sums: with S_j the sum of x - r
+                // and n_j the count over the points now labelled j, and c_j
+                // this pass's centroids, sum_i |x_i - c_a(i)|^2 = Q +
+                // sum_j (n_j |c_j - r|^2 - 2 (c_j - r).S_j).  Where the
+                // clustering leaves less than kSumsObjectiveMin of Q, the
+                // cancellation would cost digits, and the points' FP64
+                // distances are summed directly instead (which also keeps an
+                // exact zero exact).
+                __syncthreads();
+                double fp = 0.0;
+                for (int e = tid; e < k * CS; e += NT) {
+                    const int j = e / CS, t = e % CS;
+                    if (t >= d) continue;
+                    double S = 0.0, n = 0.0;
+                    for (int gg = 0; gg < copies; ++gg) {
+                        S += L.psum[(size_t)gg * k * CS + e];
+                        n += L.psum[(size_t)gg * k * CS + j * CS + D];
+                    }
+                    if (n > 0.0) {
+                        const double dc = L.C64[e] - L.ref[t];
+                        fp = __fma_rn(dc, __fma_rn(n, dc, -2.0 * S), fp);
+                    }
+                }
+                if (first) {
+                    double v2[2] = {fl, fp};
+                    block_sum_n<NT, 2>(v2, L.red);
+                    Qr = v2[0];
+                    fp = v2[1];
+                } else {
+                    fp = block_sum<NT>(fp, L.red);
+                }
+                f = Qr + fp;
+                if (!(f > kSumsObjectiveMin * Qr)) {
+                    const int64_t* ixs = a.idx + ds.idx_offset;
+                    double fe = 0.0;
+                    for (int tile = wid; tile * 16 < s; tile += NW) {
+                        const int i = tile * 16 + pl, ic = min(i, s - 1);
+                        float xq[DL];
+                        if (gathered) {
+                            load_quarter<D>(Sg + (size_t)ic * D, g, xq);
+                        } else {
+                            const int64_t r = ixs[(unsigned)ic];
+                            load_quarter<D>((r >= 0 && r < a.m) ? a.X + r * D : g_zero_row, g,
+                                            xq);
+                        }
+                        const int lab = lprev[(unsigned)ic];
+                        if (i < s) fe += quarter_part64<D>(xq, L.C64 + lab * CS);
+                    }
+                    f = block_sum<NT>(fe, L.red);
+                }
                 ++it;
                 if (it >= a.max_iter || f == 0.0 || (f_prev - f) < a.rel_tol * f_prev) break;
                 f_prev = f;
@@ -630,7 +706,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         n += L.psum[(size_t)gg * k * CS + j * CS + D];
                     }
                     double v = 0.0;
-                    if (t < d) v = n > 0.0 ? sum / n : __builtin_nan("");
+                    if (t < d) v = n > 0.0 ? L.ref[t] + sum / n : __builtin_nan("");
                     L.C64[e] = v;
                 }
                 __syncthreads();

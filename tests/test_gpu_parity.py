@@ -339,6 +339,55 @@ def test_direct_and_gathered_rows_agree(hp, orc, prec):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
+    """Warm starts read their rows straight from X (d = 16, the padded width,
+    and X 16-byte aligned).  Runs from poor starts outlast the direct-read
+    passes and switch to the gathered copy; a cluster that empties in the
+    first pass has K-means++ re-seed it from a copy gathered on the spot.
+    Every run agrees with the oracle, and with the same starts on a
+    misaligned X (rows gathered from the start)."""
+    m, d, n, s, k = 40_000, 16, 8, 3000, 12
+    Xn, _ = _mix(m, d, 12, seed=31, box=8.0, std=1.5)
+    flat = torch.zeros(m * d + 1, dtype=torch.float32, device="cuda")
+    flat[1:] = torch.from_numpy(Xn.ravel()).cuda()
+    Xmis = flat[1:].view(m, d)
+    Xal = torch.from_numpy(Xn).cuda()
+    assert Xmis.data_ptr() % 16 != 0 and Xal.data_ptr() % 16 == 0
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=4, sample_id=np.arange(n), d=d)
+    idx = hp.draw_samples(m, desc, idx_len)
+    idx_n = idx.cpu().numpy()
+    rng = np.random.default_rng(7)
+    C0 = np.stack([Xn[idx_n[b * s:(b + 1) * s]][rng.choice(s, k, replace=False)]
+                   for b in range(n)]).astype(np.float32)
+    C0[1, 3] = 1e4  # far from every point: empties in the first pass
+    C0[5, 0] = -1e4
+    outs = []
+    for Xg in (Xal, Xmis):
+        C = torch.from_numpy(C0.ravel().copy()).cuda()
+        f, it, lab = hp.lloyd_batch(Xg, idx, desc, C, want_labels=True, precision=prec)
+        outs.append((C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()))
+    (Cg, fg, itg, lg), (Cm, fm, itm, lm) = outs
+    # the FP64 sums take LDS atomics in arrival order: agreement to rounding
+    assert np.array_equal(itg, itm) and np.array_equal(lg, lm)
+    assert np.allclose(fg, fm, rtol=1e-13, atol=0) and np.allclose(Cg, Cm, rtol=1e-6, atol=1e-6)
+    assert itg.max() > 6  # some runs outlast the direct-read passes
+    checked = 0
+    for b in range(n):
+        ib = idx_n[b * s:(b + 1) * s]
+        ro = orc.lloyd(Xn, ib, k, C0[b].astype(np.float64), seed=4, sample_id=b,
+                       want_margins=True)
+        if b in (1, 5):
+            assert ro.diag["n_seed_calls"] >= 1
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        assert itg[b] == ro.iters and rel(fg[b], ro.f) <= F_REL, (b, itg[b], ro.iters)
+        assert_centroids(Cg[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, Xn[ib])
+        assert_labels(lg[b * s:(b + 1) * s], ro.labels, ro.margins)
+    assert checked >= n // 2
+
+
 def test_lloyd_batch_deterministic(hp, orc):
     Xn, Xg = _mix(50_000, 32, 25, seed=4, box=20.0, std=2.0)
     n, s, k = 40, 4000, 25
