@@ -5,7 +5,10 @@ decision the method makes -- nearest centroid, K-means++ draw, best
 candidate, stop test -- on FP64 values: FP32 screening with a rigorous
 error certificate, FP64 re-decision of uncertified points, FP64 D^2,
 potentials, sums, objectives and in-kernel centroids.  GPU and oracle FP64
-values then differ only by summation order (~1e-16 relative per term).
+values then differ only by summation order (~1e-16 relative per term); the
+GPU's pass objective, taken from the running sums, is within ~1e-12
+relative of the direct sum (it falls back to the direct sum where the
+identity would cancel).
 
 CLEAN_MARGIN   a decision whose oracle margin is below this may differ from
                the GPU's by summation-order noise; a run is "clean" when no
