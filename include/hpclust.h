@@ -37,7 +37,7 @@
  *    the k centroids (FP64, with the per-cluster sums for Lloyd) must fit a
  *    workgroup's 160 KiB of LDS.  Largest k per padded d (8, 16, 32, 64,
  *    128) for Lloyd: 512, 462, 240, 121, 60 (FP32 screening), 512, 462, 266,
- *    135, 66 (BF16); for hpc_assign_sse: 512, 512, 400, 207, 101 (FP32),
+ *    134, 66 (BF16); for hpc_assign_sse: 512, 512, 400, 207, 101 (FP32),
  *    512, 512, 480, 246, 125 (BF16).  Larger combinations are refused with
  *    HPC_ERR_UNSUPPORTED before anything is launched.
  */
@@ -204,7 +204,7 @@ int hpc_assign_sse(const float *X, int64_t m, int32_t d, const float *C, int32_t
  * ------------------------------------------------------------------------ */
 typedef struct hpc_plan_s *hpc_plan;
 
-/* Launch configuration of the resident Lloyd kernel (one workgroup of 256
+/* Launch configuration of the resident Lloyd kernel (one workgroup of 512
  * threads per sample at a time, persistent grid pulling samples from a
  * queue).  Every configuration computes the same labels, pass counts and
  * centroids up to FP64 summation order. */

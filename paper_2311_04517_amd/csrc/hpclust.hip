@@ -43,7 +43,7 @@ namespace {
 using hpc_host::fail;
 
 constexpr int kMaxD = 128;
-constexpr int kNT = 256;  // threads per workgroup of the resident kernels
+constexpr int kNT = 512;  // threads per workgroup of the resident kernels
 
 int pad_dim(int d) {
     if (d <= 8) return 8;
