@@ -222,7 +222,7 @@ typedef struct {
  * array, validated as in hpc_lloyd_batch against idx_len and c_len, copied;
  * 1 <= n_samples <= 65535) of d-dimensional data, screening precision
  * `precision`.  The plan owns its device memory (about idx_len * (4*pad(d)
- * + 12) bytes, pad(d) the next of 8, 16, 32, 64, 128) until
+ * + 44) bytes, pad(d) the next of 8, 16, 32, 64, 128) until
  * hpc_plan_destroy.  *out receives the handle (NULL on error).  The default
  * configuration is {0, 0, 0, 0}. */
 int hpc_plan_create(int32_t d, const hpc_sample_desc *desc, int32_t n_samples, int64_t idx_len,

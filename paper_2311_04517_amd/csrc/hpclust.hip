@@ -346,14 +346,14 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     const size_t order_b = (size_t)n * 4;
     const size_t sbuf_b = (size_t)idx_len * D * 4;
     const size_t need =
-        Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 8, (size_t)idx_len * 4});
+        Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 40, (size_t)idx_len * 4});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
     char* tbl = static_cast<char*>(cv.take(desc_b + order_b));
     int32_t* queue = static_cast<int32_t*>(cv.take(256));
     float* sbuf = static_cast<float*>(cv.take(sbuf_b));
-    double* d2 = static_cast<double*>(cv.take((size_t)idx_len * 8));
+    double* d2 = static_cast<double*>(cv.take((size_t)idx_len * 40));
     int32_t* lbuf = static_cast<int32_t*>(cv.take((size_t)idx_len * 4));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
@@ -714,7 +714,7 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     const size_t desc_b = (size_t)n_samples * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n_samples * 8;
     const size_t sbuf_b = (size_t)idx_len * p->D * 4;
-    const size_t d2_b = (size_t)idx_len * 8;
+    const size_t d2_b = (size_t)idx_len * 40;  // D^2 and up to four candidate distances
     const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)idx_len * 4,
                                      (size_t)c_len * 4, (size_t)n_samples * 8,
                                      (size_t)n_samples * 4});

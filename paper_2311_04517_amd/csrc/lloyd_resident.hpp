@@ -55,7 +55,8 @@ struct LloydArgs {
     int32_t* iters_out;
     int32_t* labels_out;
     float* sbuf;    // gathered samples, indexed by idx_offset, stride D
-    double* d2buf;  // D^2, indexed by idx_offset
+    double* d2buf;  // per sample, at 5 * idx_offset: D^2 (s) and the
+                    // distances to the K-means++ candidates of a step (4 x s)
     int32_t* lbuf;  // label of each sample point in the previous pass, by idx_offset
     int32_t* queue;
     int32_t kmax;
@@ -207,6 +208,7 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
 
     const int cw = (((s + NW - 1) / NW) + 15) / 16 * 16;
     const int lo = min(s, wid * cw), hi = min(s, lo + cw);
+    double* __restrict__ vc = d2 + s;  // candidate distances, n_cand x s
     auto load_pt = [&](int i, float (&xq)[DL]) {
         if (i < hi) {
             load_quarter<D>(sv.row(i), g, xq);
@@ -267,7 +269,7 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
         const double c_hi = c_lo + L.red[wid];
         const uint64_t q = (uint64_t)(r + (n_valid > 0 ? 1 : 0));
         const Words4 w = philox_block(seed, tag, q, sid, call);
-        int pick;
+        int pick, tsel = -1;
         if (!(W > 0.0)) {
             pick = (int)bounded_index(w.w[0], (uint64_t)s);
             __syncthreads();
@@ -332,7 +334,10 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
                 for (int t = 0; t < 4; ++t) {
                     if (t >= n_cand) continue;
                     const double v = quarter_dist64<D>(xq, L.crow + t * D);
-                    if (i < hi && g == 0) pt[t] += v < dd ? v : dd;
+                    if (i < hi && g == 0) {
+                        pt[t] += v < dd ? v : dd;
+                        vc[(size_t)t * s + i] = v;  // the D^2 update reads it back
+                    }
                 }
             }
             block_sum_n<NT, 4>(pt, L.red);
@@ -345,22 +350,38 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
                     tb = t;
                 }
             pick = L.ints[4 + tb];
+            tsel = tb;
         }
         const int jr = L.deg[r];
         if (tid == 0 && chosen) chosen[jr] = pick;
         set_row_from_sample<D, NT>(L.C64 + jr * CS, sv, pick);
         __syncthreads();
         acc = 0.0;
-        for (int b0 = lo; b0 < hi; b0 += 16) {
-            const int i = b0 + p;
-            float xq[DL];
-            load_pt(i, xq);
-            const double v = quarter_dist64<D>(xq, L.C64 + jr * CS);
-            if (i < hi && g == 0) {
-                const double o = d2[i];
-                const double nv = v < o ? v : o;
-                d2[i] = nv;
-                acc += nv;
+        if (tsel >= 0) {
+            // the chosen candidate's distances were stored by the lanes
+            // that read them back: no second pass over the rows
+            const double* vt = vc + (size_t)tsel * s;
+            for (int b0 = lo; b0 < hi; b0 += 16) {
+                const int i = b0 + p;
+                if (i < hi && g == 0) {
+                    const double v = vt[i], o = d2[i];
+                    const double nv = v < o ? v : o;
+                    d2[i] = nv;
+                    acc += nv;
+                }
+            }
+        } else {
+            for (int b0 = lo; b0 < hi; b0 += 16) {
+                const int i = b0 + p;
+                float xq[DL];
+                load_pt(i, xq);
+                const double v = quarter_dist64<D>(xq, L.C64 + jr * CS);
+                if (i < hi && g == 0) {
+                    const double o = d2[i];
+                    const double nv = v < o ? v : o;
+                    d2[i] = nv;
+                    acc += nv;
+                }
             }
         }
         __syncthreads();
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         const int s = ds.s, k = ds.k;
         const int nblk = (k + 15) / 16;
         float* Sg = a.sbuf + (size_t)ds.idx_offset * D;
-        double* d2 = a.d2buf + ds.idx_offset;
+        double* d2 = a.d2buf + 5 * (size_t)ds.idx_offset;
         int32_t* lprev = a.lbuf + ds.idx_offset;
         int32_t* lab_out = a.labels_out ? a.labels_out + ds.idx_offset : nullptr;
         const SampleView<D> sv{Sg};
