@@ -60,8 +60,11 @@ __host__ __device__ inline size_t assign_lds_bytes(int k, int nt) {
     return b;
 }
 
+// Up to d = 32 five waves per SIMD, each with three tiles of rows in
+// flight; wider rows keep three register buffers at the occupancy their
+// registers allow.
 template <int D, int NT, int PREC>
-__global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, int64_t m, int d,
+__global__ __launch_bounds__(NT, D <= 32 ? 5 : (D <= 64 ? 3 : 2)) void k_assign_sse(const float* __restrict__ X, int64_t m, int d,
                                                    const float* __restrict__ C, int k,
                                                    int32_t* __restrict__ labels,
                                                    unsigned long long* __restrict__ counts,
@@ -140,26 +143,44 @@ __global__ __launch_bounds__(NT) void k_assign_sse(const float* __restrict__ X, 
     };
     const int64_t first = (int64_t)blockIdx.x * NW + wid, stride = (int64_t)gridDim.x * NW;
     if (vec) {
-        // rows of D floats, 16-byte aligned: software pipelined over three
-        // register buffers (rows of the next two tiles in flight while one
-        // is processed); rows past the end re-read the last row, branch-free
+        // rows of D floats, 16-byte aligned: software pipelined over register
+        // buffers (rows of the next tiles in flight while one is processed;
+        // unrolled so that no buffer with a load in flight is copied); rows
+        // past the end re-read the last row, branch-free, and tiles past the
+        // end are skipped by wave-uniform guards rather than exits from the
+        // unrolled body
         auto fetch = [&](int64_t tile, float (&dst)[DL]) {
             int64_t i = tile * 16 + (lane & 15);
             i = i < m ? i : m - 1;
             load_quarter<D>(X + i * D, g, dst);
         };
-        float xa[DL], xb[DL], xc[DL];
-        fetch(first, xa);
-        fetch(first + stride, xb);
-        for (int64_t tile = first; tile < n_tiles; tile += 3 * stride) {
-            fetch(tile + 2 * stride, xc);
-            process(tile, xa);
-            if (tile + stride >= n_tiles) break;
-            fetch(tile + 3 * stride, xa);
-            process(tile + stride, xb);
-            if (tile + 2 * stride >= n_tiles) break;
-            fetch(tile + 4 * stride, xb);
-            process(tile + 2 * stride, xc);
+        if constexpr (D <= 32) {
+            float xa[DL], xb[DL], xc[DL], xd[DL];
+            fetch(first, xa);
+            fetch(first + stride, xb);
+            fetch(first + 2 * stride, xc);
+            for (int64_t tile = first; tile < n_tiles; tile += 4 * stride) {
+                fetch(tile + 3 * stride, xd);
+                process(tile, xa);
+                fetch(tile + 4 * stride, xa);
+                if (tile + stride < n_tiles) process(tile + stride, xb);
+                fetch(tile + 5 * stride, xb);
+                if (tile + 2 * stride < n_tiles) process(tile + 2 * stride, xc);
+                fetch(tile + 6 * stride, xc);
+                if (tile + 3 * stride < n_tiles) process(tile + 3 * stride, xd);
+            }
+        } else {
+            float xa[DL], xb[DL], xc[DL];
+            fetch(first, xa);
+            fetch(first + stride, xb);
+            for (int64_t tile = first; tile < n_tiles; tile += 3 * stride) {
+                fetch(tile + 2 * stride, xc);
+                process(tile, xa);
+                fetch(tile + 3 * stride, xa);
+                if (tile + stride < n_tiles) process(tile + stride, xb);
+                fetch(tile + 4 * stride, xb);
+                if (tile + 2 * stride < n_tiles) process(tile + 2 * stride, xc);
+            }
         }
     } else {
         for (int64_t tile = first; tile < n_tiles; tile += stride) {
