@@ -152,6 +152,11 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  *     c_len, the lengths of idx and C).
  *   precision: HPC_PREC_FP32 or HPC_PREC_BF16_MFMA (screening type, see
  *     above; labels, f and centroids do not depend on it).
+ *   f is evaluated in FP64 from the per-cluster sums of x - r and counts (r
+ *     a reference point fixed per sample): Q + sum_j (n_j |c_j - r|^2 -
+ *     2 (c_j - r).S_j), Q = sum |x - r|^2, within about 1e-12 relative of
+ *     the direct sum; where f is below 1% of Q, the identity would cancel
+ *     and the points' FP64 distances are summed directly.
  *   f_out (device double[n]), iters_out (device int32[n]); labels_out
  *   nullable (device int32[idx_len]).
  * Samples may be processed in any order and concurrently; each sample's

@@ -388,6 +388,35 @@ def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
     assert checked >= n // 2
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_lloyd_tight_clusters_sum_the_objective_directly(hp, orc, prec):
+    """Tight clusters far apart: the objective is a tiny fraction of the
+    scatter about the reference point, so each pass sums the points' FP64
+    distances instead of taking the objective from the running sums; pass
+    counts, objectives, centroids and labels still match the oracle."""
+    m, d, n, s, k = 20_000, 8, 4, 3000, 6
+    Xn, Xg = _mix(m, d, 6, seed=41, box=20.0, std=0.05)
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=6, sample_id=np.arange(n), d=d)
+    idx = hp.draw_samples(m, desc, idx_len)
+    idx_n = idx.cpu().numpy()
+    C = torch.full((c_len,), float("nan"), device="cuda")
+    f, it, lab = hp.lloyd_batch(Xg, idx, desc, C, want_labels=True, precision=prec)
+    Cg, fg, itg, lg = C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()
+    checked = 0
+    for b in range(n):
+        ib = idx_n[b * s:(b + 1) * s]
+        ro = orc.lloyd(Xn, ib, k, seed=6, sample_id=b, want_margins=True)
+        S = Xn[ib].astype(np.float64)
+        assert ro.f < 1e-2 * ((S - S.mean(0)) ** 2).sum()  # the direct-sum regime
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        assert itg[b] == ro.iters and rel(fg[b], ro.f) <= F_REL, (b, itg[b], ro.iters)
+        assert_centroids(Cg[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, S)
+        assert_labels(lg[b * s:(b + 1) * s], ro.labels, ro.margins)
+    assert checked >= n // 2
+
+
 def test_lloyd_batch_deterministic(hp, orc):
     Xn, Xg = _mix(50_000, 32, 25, seed=4, box=20.0, std=2.0)
     n, s, k = 40, 4000, 25
