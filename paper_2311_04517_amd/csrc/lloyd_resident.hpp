@@ -29,7 +29,7 @@
 namespace hpc {
 
 // Passes a warm sample reads straight from X before it gathers its rows.
-constexpr int kDirectPasses = 6;
+constexpr int kDirectPasses = 15;
 
 // Smallest objective, relative to the sample's scatter Q about its
 // reference point, that is taken from the running sums (below it the
@@ -513,9 +513,10 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             for (;;) {
                 // reading rows through the indices costs more per pass than
                 // reading the gathered copy (scattered 128-byte rows against
-                // contiguous ones; about a seventh of the copy's cost): a
-                // sample still running after kDirectPasses passes makes the
-                // copy, which bounds the loss to twice the better choice
+                // contiguous ones; measured at about a fifteenth of the
+                // copy's cost): a sample still running after kDirectPasses
+                // passes makes the copy, which bounds the loss to about twice
+                // the better choice made in hindsight
                 if (!gathered && it > 0 && (it >= kDirectPasses || any_degenerate())) {
                     gather();
                     gathered = true;

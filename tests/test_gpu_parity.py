@@ -342,13 +342,14 @@ def test_direct_and_gathered_rows_agree(hp, orc, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
     """Warm starts read their rows straight from X (d = 16, the padded width,
-    and X 16-byte aligned).  Runs from poor starts outlast the direct-read
-    passes and switch to the gathered copy; a cluster that empties in the
-    first pass has K-means++ re-seed it from a copy gathered on the spot.
-    Every run agrees with the oracle, and with the same starts on a
-    misaligned X (rows gathered from the start)."""
+    and X 16-byte aligned).  On structureless (uniform) data runs from
+    random starts take 20-35 passes, outlast the direct-read passes and
+    switch to the gathered copy; a cluster that empties in the first pass
+    has K-means++ re-seed it from a copy gathered on the spot.  Every run
+    agrees with the oracle, and with the same starts on a misaligned X (rows
+    gathered from the start)."""
     m, d, n, s, k = 40_000, 16, 8, 3000, 12
-    Xn, _ = _mix(m, d, 12, seed=31, box=8.0, std=1.5)
+    Xn = torch.rand(m, d, generator=torch.Generator().manual_seed(31)).numpy()
     flat = torch.zeros(m * d + 1, dtype=torch.float32, device="cuda")
     flat[1:] = torch.from_numpy(Xn.ravel()).cuda()
     Xmis = flat[1:].view(m, d)
@@ -371,7 +372,7 @@ def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
     # the FP64 sums take LDS atomics in arrival order: agreement to rounding
     assert np.array_equal(itg, itm) and np.array_equal(lg, lm)
     assert np.allclose(fg, fm, rtol=1e-13, atol=0) and np.allclose(Cg, Cm, rtol=1e-6, atol=1e-6)
-    assert itg.max() > 6  # some runs outlast the direct-read passes
+    assert itg.max() > 15  # some runs outlast the direct-read passes
     checked = 0
     for b in range(n):
         ib = idx_n[b * s:(b + 1) * s]
