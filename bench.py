@@ -13,6 +13,11 @@ of the best worker, and the full-data assignment with its FP64 objective.
 
 metric: sample-point-iters/s = sum over samples of s x assignment passes,
 divided by the wall time of the timed steps (inputs resident in HBM).
+
+--workload precision runs the same rounds on the precision workload (m =
+10^8, d = 64, 100 rotated anisotropic components, k = 100, 128 workers of
+50,000 points, BF16 screening) and reports the distance tiles' useful MFMA
+rate (2 k d flop per sample-point-iter) against the MFMA peak.
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense, MI355X
 
 
 def parse():
@@ -33,15 +39,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=10_000_000)
-    ap.add_argument("--workers", type=int, default=1024)
-    ap.add_argument("--s", type=int, default=10_000)
-    ap.add_argument("--k", type=int, default=25)
+    ap.add_argument("--workload", choices=["metric", "precision"], default="metric",
+                    help="metric: m = 1e7, d = 32, k = 25, 1,024 workers of 10,000 points "
+                         "(the headline); precision: m = 1e8, d = 64, 100 rotated anisotropic "
+                         "components, k = 100, 128 workers of 50,000 points, BF16 screening "
+                         "(reports the distance tiles' MFMA rate)")
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--workers", type=int, default=None)
+    ap.add_argument("--s", type=int, default=None)
+    ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables it)")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
-                    help="MFMA type of the distance screening (decisions are FP64-exact)")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+                    help="MFMA type of the distance screening (decisions are FP64-exact); "
+                         "default fp32 for the metric workload, bf16 for the precision one")
     ap.add_argument("--no-other-precision", dest="other_precision", action="store_false",
                     help="skip the same measurement with the other screening precision")
     ap.add_argument("--no-tts", dest="tts", action="store_false",
@@ -57,7 +69,15 @@ def parse():
                     help="run one launch of each kernel for counter collection (a 1 GiB "
                          "calibration copy, a cold batch, a warm 3-pass batch, one full "
                          "assignment) and exit")
-    return ap.parse_args()
+    a = ap.parse_args()
+    dflt = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="fp32"),
+            "precision": dict(m=100_000_000, workers=128, s=50_000, k=100, precision="bf16")}
+    for key, v in dflt[a.workload].items():
+        if getattr(a, key) is None:
+            setattr(a, key, v)
+    if a.workload == "precision":
+        a.tts = False  # the time-to-SSE comparison is defined on the metric workload
+    return a
 
 
 def main():
@@ -78,7 +98,10 @@ def main():
     print(f"[bench] {api.version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr,
           flush=True)
     t_gen = time.perf_counter()
-    mx = synthetic.metric_set(m=args.m, device=dev)
+    if args.workload == "precision":
+        mx = synthetic.precision_set(m=args.m, device=dev)
+    else:
+        mx = synthetic.metric_set(m=args.m, device=dev)
     X = mx.X
     torch.cuda.synchronize()
     print(f"[bench] data {tuple(X.shape)} generated in {time.perf_counter() - t_gen:.1f}s",
@@ -105,7 +128,7 @@ def main():
     # to this launch's units of work (null if the kernels changed since)
     traffic = None
     rec = measured_traffic(f"lloyd_resident_metric_traffic_{'bf16' if prec else 'fp32'}.json")
-    if rec is not None:
+    if rec is not None and args.workload == "metric":
         units = float(passes.mean()) * s
         traffic = {"bytes_per_launch": rec["bytes_per_unit"] * units,
                    "read_bytes_per_unit": rec["read_bytes_per_unit"],
@@ -119,8 +142,31 @@ def main():
         f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
         tts = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
 
+    D = 1 << max(3, (d - 1).bit_length())  # padded width of the kernel instantiation
+    roofline = {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"k_lloyd_resident<{D},512,{prec}>", "launch": tune,
+                "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
+                "avg_launch_ms": t_lloyd * 1e3,
+                "frac_of_copy": lloyd_gbs / copy["gbs"]}
+    assign = {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,
+              "frac": assign_gbs / HBM_PEAK_GBS, "frac_of_copy": assign_gbs / copy["gbs"]}
+    if args.workload == "precision":
+        # the distance tiles: useful cross-term flops 2 k d per sample-point
+        # pass (unpadded k and d) against the MFMA peak of the screening type
+        peak = MFMA_PEAK_TFLOPS["bf16" if prec else "fp32"]
+        spi = float(passes.mean()) * s
+        tflops = 2.0 * k * d * spi / t_lloyd / 1e12
+        roofline = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                    "frac": tflops / peak, "traffic": None,
+                    "kernel": f"k_lloyd_resident<{D},512,{prec}>", "launch": tune,
+                    "flops_per_unit": 2 * k * d, "unit_of_work": "sample-point-iter",
+                    "avg_launch_ms": t_lloyd * 1e3, "hbm_gbs": lloyd_gbs,
+                    "hbm_frac": lloyd_gbs / HBM_PEAK_GBS, "frac_of_copy": lloyd_gbs / copy["gbs"]}
+        assign["tflops"] = 2.0 * k * d * m / t_assign / 1e12
+        assign["mfma_frac"] = assign["tflops"] / peak
     out = {
-        "metric": "sample-point-iters/sec (k=25,d=32)",
+        "metric": f"sample-point-iters/sec (k={k},d={d})",
         "value": value,
         "unit": "sample-point-iters/s",
         "n_gpus": 1,
@@ -132,18 +178,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "fp32" else "bf16+f64",
         "data": "synthetic",
-        "config": {"workload": "gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round",
+        "config": {"workload": ("gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round"
+                                if args.workload == "metric" else
+                                "gmm100 rotated m=1e8 d=64 k=100 s=5e4 workers=128 competitive round"),
                    "m": m, "d": d, "k": k, "s": s, "workers": W, "strategy": "competitive",
                    "passes_per_step": float(passes.mean())},
-        "roofline": {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": lloyd_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_lloyd_resident<32,512,{prec}>", "launch": tune,
-                     "bytes_per_unit": 4 * d, "unit_of_work": "sample-point-iter",
-                     "avg_launch_ms": t_lloyd * 1e3,
-                     "frac_of_copy": lloyd_gbs / copy["gbs"]},
-        "assign_sse": {"avg_launch_ms": t_assign * 1e3, "achieved_gbs": assign_gbs,
-                       "frac": assign_gbs / HBM_PEAK_GBS,
-                       "frac_of_copy": assign_gbs / copy["gbs"]},
+        "roofline": roofline,
+        "assign_sse": assign,
         "hbm_copy": copy,
         "cpu_baseline": cpu,
         "time_to_sse": tts,

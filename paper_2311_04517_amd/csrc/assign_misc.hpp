@@ -125,12 +125,13 @@ __global__ __launch_bounds__(NT, D <= 32 ? 5 : (D <= 64 ? 3 : 2)) void k_assign_
         const bool valid = i < m;
         const float xn2 = point_norm2<D>(xq);
         const float xn = cert_norm(xn2);
-        const Top3 t3 =
-            screen_tile<D, PREC>(xq, aop, nrm, nblk, screen_shift(xn2, xn, ea, eb), kmask);
+        const float h = screen_shift(xn2, xn, ea, eb);
+        const Top3 t3 = screen_tile<D, PREC>(xq, aop, nrm, nblk, h, kmask);
         const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
         const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
-        int am = redecide64<D>(xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb),
-                               a1 < k ? a1 : 0, a2 < k ? a2 : 0, C64, k);
+        int am = redecide64<D, PREC>(xq, t3, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb),
+                                     a1 < k ? a1 : 0, a2 < k ? a2 : 0, C64, aop, nrm, nblk, h,
+                                     kmask, qscale, xn, ea, eb);
         if (valid) {
             // this lane's share of the objective: FP64 distance to the choice
             fl += n_valid > 0 ? quarter_part64<D>(xq, C64 + am * CS) : __builtin_huge_val();

@@ -568,13 +568,13 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     const bool valid = i < s;
                     const float xn2 = point_norm2<D>(xq);
                     const float xn = cert_norm(xn2);
-                    const Top3 t3 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk,
-                                                         screen_shift(xn2, xn, ea, eb), kmask);
+                    const float h = screen_shift(xn2, xn, ea, eb);
+                    const Top3 t3 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk, h, kmask);
                     const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
                     const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
-                    const int am = redecide64<D>(
-                        xq, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb), a1,
-                        a2 < k ? a2 : a1, L.C64, k);
+                    const int am = redecide64<D, PREC>(
+                        xq, t3, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb), a1,
+                        a2 < k ? a2 : a1, L.C64, L.aop, L.nrm, nblk, h, kmask, qscale, xn, ea, eb);
                     if (valid) {
                         // a point that changed cluster moves x - r between the
                         // running sums (padded coordinates of x and r are

@@ -44,7 +44,7 @@
 // test below uses the stronger  q_2 - q_1 > 2.5 E + 2^(NB-20) q_2  (the
 // left side grows faster in q_j than the right, so the runner-up is the
 // binding case).  The same test on the third key shows the exact argmin is
-// one of the two best.
+// one of the two best, and on any row j that j is not the argmin.
 #pragma once
 
 #include "common.hpp"
@@ -291,6 +291,26 @@ __device__ __forceinline__ double quarter_dist64(const float (&xq)[Lay<D>::DL],
     return pair_sum<32>(pair_sum<16>(p));
 }
 
+// quarter_dist64 for use inside loops: the point's coordinates are
+// converted to FP64 at each call (the empty asm hides that they are
+// loop-invariant, so the compiler does not hoist the conversions and hold
+// 2 DL registers for the whole loop).
+template <int D>
+__device__ __forceinline__ double quarter_dist64_fresh(const float (&xq)[Lay<D>::DL],
+                                                       const double* __restrict__ c) {
+    constexpr int DL = Lay<D>::DL;
+    const int g = (threadIdx.x & 63) >> 4;
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < DL; ++t) {
+        float x = xq[t];
+        asm volatile("" : "+v"(x));
+        const double e = (double)x - c[g * DL + t];
+        p = __fma_rn(e, e, p);
+    }
+    return pair_sum<32>(pair_sum<16>(p));
+}
+
 // |x| for the certificate: hardware square root (within 1 ulp), the 2.5
 // factor of the test covers its error.
 __device__ __forceinline__ float cert_norm(float n2) { return __builtin_amdgcn_sqrtf(n2); }
@@ -313,32 +333,101 @@ __device__ __forceinline__ bool top2_suffices(const Top3& t, unsigned kmask, flo
     return (q3 - q1) > 2.5f * (ea * xnorm + eb) + qscale * q3;
 }
 
+// Rows that may still hold the exact minimum of this lane's point when its
+// three best keys leave more than two in contention (`full`): the screening
+// tile is computed again, and every row whose key fails the certificate's
+// exclusion test against the best key q1 (q_j - q1 > 2.5 E + 2^(NB-20) q_j;
+// the argument above shows an excluded row scores strictly above the
+// screening winner, so exact ties are never excluded) is ranked in FP64.
+// Each such row is evaluated once for all points of the wave that keep it
+// (wave-uniform loops over ballots).  best / bj carry the exact value and
+// index of the best row so far and are updated in place, lowest index on
+// exact ties.  Padding and invalid rows (keys at or above 0x7F800000) are
+// never kept.
+template <int D, int PREC>
+__device__ __forceinline__ void rescan_rows(const float (&xq)[Lay<D>::DL], bool full, float q1,
+                                            float e25, float qscale, const void* __restrict__ aop,
+                                            const float* __restrict__ nrm, int nblk, float h,
+                                            unsigned kmask, const double* __restrict__ C64,
+                                            double& best, int& bj) {
+    constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC, CS = Lay<D>::CS;
+    const int lane = threadIdx.x & 63, g = lane >> 4, p = lane & 15;
+    for (int blk = 0; blk < nblk; ++blk) {
+        f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+        if constexpr (PREC == kPrecF32) {
+            const float* a = static_cast<const float*>(aop);
+#pragma unroll
+            for (int q = 0; q < DL; ++q)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
+                                                           acc, 0, 0, 0);
+        } else {
+            const bf16x8* a = static_cast<const bf16x8*>(aop);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                bf16x8 xb;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int q = kc * 8 + v;
+                    xb[v] = (__bf16)(q < DL ? xq[q < DL ? q : 0] : 0.f);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[(blk * KC + kc) * 64 + lane], xb,
+                                                              acc, 0, 0, 0);
+            }
+        }
+        // kept rows of this block: bit 16 g' + p' of keep[r] is row 4 g' + r
+        // for point p'
+        unsigned long long keep[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const unsigned key = screen_key(acc[r] + h, kmask, 0u);
+            const float q = key_value(key, kmask);
+            keep[r] = __ballot(full && key < 0x7F800000u && !((q - q1) > e25 + qscale * q));
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            unsigned long long mk = keep[r];
+            while (mk) {
+                const int gg = __builtin_ctzll(mk) >> 4;
+                const unsigned bits = (unsigned)(mk >> (16 * gg)) & 0xFFFFu;
+                mk &= ~(0xFFFFull << (16 * gg));
+                const int j = blk * 16 + 4 * gg + r;
+                const double v = quarter_dist64_fresh<D>(xq, C64 + j * CS);
+                if (((bits >> p) & 1u) && (v < best || (v == best && j < bj))) {
+                    best = v;
+                    bj = j;
+                }
+            }
+        }
+    }
+}
+
 // Exact FP64 decision for the points of this wave whose screening was not
 // certified (`redo` true in their four lanes): between the two best
-// screened centroids when the third is clear (`pair_ok`), otherwise over
-// all k rows.  Lowest index on exact ties.  Wave-uniform loops; returns the
-// decided index (a1 where redo is false).
-template <int D>
-__device__ __forceinline__ int redecide64(const float (&xq)[Lay<D>::DL], bool redo, bool pair_ok,
-                                          int a1, int a2, const double* __restrict__ C64, int k) {
+// screened rows when the third is clear (`pair_ok`), otherwise over the
+// rows rescan_rows keeps.  Lowest index on exact ties.  Wave-uniform
+// branches; returns the decided index (a1 where redo is false).  h, xnorm,
+// ea and eb are the values the point's keys t were screened with.
+template <int D, int PREC>
+__device__ __forceinline__ int redecide64(const float (&xq)[Lay<D>::DL], const Top3& t, bool redo,
+                                          bool pair_ok, int a1, int a2,
+                                          const double* __restrict__ C64,
+                                          const void* __restrict__ aop,
+                                          const float* __restrict__ nrm, int nblk, float h,
+                                          unsigned kmask, float qscale, float xnorm, float ea,
+                                          float eb) {
     constexpr int CS = Lay<D>::CS;
     int am = a1;
     if (!__any(redo)) return am;
     const double v1 = quarter_dist64<D>(xq, C64 + a1 * CS);
     const double v2 = quarter_dist64<D>(xq, C64 + a2 * CS);
-    if (redo && pair_ok && (v2 < v1 || (v2 == v1 && a2 < a1))) am = a2;
+    const bool take2 = v2 < v1 || (v2 == v1 && a2 < a1);
+    if (redo && pair_ok && take2) am = a2;
     const bool full = redo && !pair_ok;
     if (!__any(full)) return am;
-    double best = __builtin_huge_val();
-    int bj = 0;
-    for (int j = 0; j < k; ++j) {
-        if (C64[j * CS] != C64[j * CS]) continue;
-        const double v = quarter_dist64<D>(xq, C64 + j * CS);
-        if (v < best) {
-            best = v;
-            bj = j;
-        }
-    }
+    double best = take2 ? v2 : v1;
+    int bj = take2 ? a2 : a1;
+    rescan_rows<D, PREC>(xq, full, key_value(t.t1, kmask), 2.5f * (ea * xnorm + eb), qscale, aop,
+                         nrm, nblk, h, kmask, C64, best, bj);
     return full ? bj : am;
 }
 

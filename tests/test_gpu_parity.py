@@ -316,6 +316,43 @@ def test_near_ties_are_redecided_exactly(hp, orc, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_crowded_centroids_are_rescanned_exactly(hp, orc, prec):
+    """Groups of four centroids 0.05 apart, far from the origin: for most
+    points the three best screened keys are all within the screening error,
+    so neither the winner nor the best two are certified and the decision
+    goes to the FP64 rescan of every row the screening cannot exclude.
+    k = 100 leaves padding rows in the last block of 16, and a NaN row
+    inside a group must never be chosen."""
+    rng = np.random.default_rng(11)
+    d, groups, m = 64, 25, 30_000
+    G = rng.uniform(-20, 20, size=(groups, d)) + 40.0
+    Cn = (np.repeat(G, 4, axis=0) + rng.normal(0, 0.05, size=(4 * groups, d))).astype(np.float32)
+    Cn[5] = np.nan
+    k = Cn.shape[0]
+    Xn = (G[rng.integers(0, groups, size=m)] + rng.normal(0, 1.0, size=(m, d))).astype(np.float32)
+    o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
+    D2 = ((Xn[:, None, :].astype(np.float64) - np.where(np.isnan(Cn), np.inf, Cn)[None]) ** 2).sum(2)
+    D2.sort(1)
+    assert (D2[:, 2] - D2[:, 0] < 20.0).mean() > 0.9  # three rows in contention almost everywhere
+    Xg = torch.from_numpy(Xn).cuda()
+    lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda(), precision=prec)
+    lg = lab.cpu().numpy()
+    assert_labels(lg, o["labels"], o["margins"])
+    assert (lg != 5).all()
+    assert np.array_equal(cnt.cpu().numpy(), np.bincount(lg, minlength=k))
+    assert rel(sse.item(), o["sse"]) <= SSE_REL
+    # the same decisions inside Lloyd: one pass from these centroids (all
+    # valid, since Lloyd seeds NaN rows)
+    Cl = Cn.copy()
+    Cl[5] = (G[1] + rng.normal(0, 0.05, size=d)).astype(np.float32)
+    ol = orc.assign_sse(Xn, Cl.astype(np.float64), want_margins=True)
+    idx = np.arange(m, dtype=np.int64)
+    desc, _, _ = hp.make_desc([m], [k], seed=2, sample_id=[0], d=d)
+    Cg, fg, itg, lg2 = _lloyd_gpu(hp, Xg, idx, desc, Cl, max_iter=1, precision=prec)
+    assert_labels(lg2, ol["labels"], ol["margins"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_direct_and_gathered_rows_agree(hp, orc, prec):
     """Rows read straight from X through the indices (d equal to the padded
     width, aligned X) and rows gathered into scratch (misaligned X) give
