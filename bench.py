@@ -16,8 +16,14 @@ divided by the wall time of the timed steps (inputs resident in HBM).
 
 --workload precision runs the same rounds on the precision workload (m =
 10^8, d = 64, 100 rotated anisotropic components, k = 100, 128 workers of
-50,000 points, BF16 screening) and reports the distance tiles' useful MFMA
-rate (2 k d flop per sample-point-iter) against the MFMA peak.
+50,000 points, BF16x3 screening) and reports the distance tiles' useful MFMA
+rate (2 k d flop per sample-point-iter) against the BF16 MFMA peak.
+
+Every screening type (FP32, BF16, BF16x3) only proposes the nearest
+centroid; each decision is certified or re-taken in FP64, so pass counts,
+labels, centroids, f and SSE are the same for all three (the JSON line
+reports whether they were).  The default is the fastest type per workload:
+BF16 for the metric workload, BF16x3 for the precision one.
 """
 from __future__ import annotations
 
@@ -31,7 +37,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense, MI355X
+# screening types: ABI code, dtype label, dense MFMA peak of the instruction
+# they run on (TFLOP/s, MI355X)
+SCREENINGS = {"fp32": (0, "f32+f64", 157.3), "bf16": (1, "bf16+f64", 2500.0),
+              "bf16x3": (2, "bf16x3+f64", 2500.0)}
 
 
 def parse():
@@ -42,7 +51,7 @@ def parse():
     ap.add_argument("--workload", choices=["metric", "precision"], default="metric",
                     help="metric: m = 1e7, d = 32, k = 25, 1,024 workers of 10,000 points "
                          "(the headline); precision: m = 1e8, d = 64, 100 rotated anisotropic "
-                         "components, k = 100, 128 workers of 50,000 points, BF16 screening "
+                         "components, k = 100, 128 workers of 50,000 points, BF16x3 screening "
                          "(reports the distance tiles' MFMA rate)")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--workers", type=int, default=None)
@@ -51,11 +60,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables it)")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+    ap.add_argument("--precision", choices=list(SCREENINGS), default=None,
                     help="MFMA type of the distance screening (decisions are FP64-exact); "
-                         "default fp32 for the metric workload, bf16 for the precision one")
+                         "default bf16 for the metric workload, bf16x3 for the precision one")
     ap.add_argument("--no-other-precision", dest="other_precision", action="store_false",
-                    help="skip the same measurement with the other screening precision")
+                    help="skip the same measurement with the other screening types")
     ap.add_argument("--no-tts", dest="tts", action="store_false",
                     help="skip the time-to-SSE comparison")
     ap.add_argument("--tts-samples", type=int, default=64,
@@ -70,8 +79,8 @@ def parse():
                          "calibration copy, a cold batch, a warm 3-pass batch, one full "
                          "assignment) and exit")
     a = ap.parse_args()
-    dflt = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="fp32"),
-            "precision": dict(m=100_000_000, workers=128, s=50_000, k=100, precision="bf16")}
+    dflt = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="bf16"),
+            "precision": dict(m=100_000_000, workers=128, s=50_000, k=100, precision="bf16x3")}
     for key, v in dflt[a.workload].items():
         if getattr(a, key) is None:
             setattr(a, key, v)
@@ -108,17 +117,18 @@ def main():
           file=sys.stderr, flush=True)
     m, d = X.shape
     W, s, k = args.workers, args.s, args.k
-    prec = api.PREC_BF16_MFMA if args.precision == "bf16" else api.PREC_FP32
+    prec = SCREENINGS[args.precision][0]
     if args.pmc_target:
         pmc_target(api, X, m, d, W, s, k, prec, args.seed)
         return
 
     copy = copy_bandwidth()
     main_res = run_metric(api, X, args, prec)
-    other = None
+    others = {}
     if args.other_precision:
-        oprec = api.PREC_FP32 if prec == api.PREC_BF16_MFMA else api.PREC_BF16_MFMA
-        other = run_metric(api, X, args, oprec)
+        for name, (code, _, _) in SCREENINGS.items():
+            if name != args.precision:
+                others[name] = run_metric(api, X, args, code)
     value, elapsed, passes = main_res["value"], main_res["elapsed"], main_res["passes"]
     t_lloyd, t_assign = main_res["t_lloyd"], main_res["t_assign"]
     lloyd_gbs, assign_gbs, tune = main_res["lloyd_gbs"], main_res["assign_gbs"], main_res["tune"]
@@ -127,7 +137,7 @@ def main():
     # HBM traffic per launch from the committed counter measurement, scaled
     # to this launch's units of work (null if the kernels changed since)
     traffic = None
-    rec = measured_traffic(f"lloyd_resident_metric_traffic_{'bf16' if prec else 'fp32'}.json")
+    rec = measured_traffic(f"lloyd_resident_metric_traffic_{args.precision}.json")
     if rec is not None and args.workload == "metric":
         units = float(passes.mean()) * s
         traffic = {"bytes_per_launch": rec["bytes_per_unit"] * units,
@@ -154,7 +164,7 @@ def main():
     if args.workload == "precision":
         # the distance tiles: useful cross-term flops 2 k d per sample-point
         # pass (unpadded k and d) against the MFMA peak of the screening type
-        peak = MFMA_PEAK_TFLOPS["bf16" if prec else "fp32"]
+        peak = SCREENINGS[args.precision][2]
         spi = float(passes.mean()) * s
         tflops = 2.0 * k * d * spi / t_lloyd / 1e12
         roofline = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
@@ -176,7 +186,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "fp32" else "bf16+f64",
+        "dtype": SCREENINGS[args.precision][1],
         "data": "synthetic",
         "config": {"workload": ("gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round"
                                 if args.workload == "metric" else
@@ -189,17 +199,21 @@ def main():
         "cpu_baseline": cpu,
         "time_to_sse": tts,
     }
-    if other is not None:
-        out["other_screening"] = {
-            "dtype": "bf16+f64" if prec == api.PREC_FP32 else "f32+f64",
-            "value": other["value"], "ms_per_step": other["elapsed"] / args.steps * 1e3,
-            "lloyd_avg_launch_ms": other["t_lloyd"] * 1e3, "lloyd_gbs": other["lloyd_gbs"],
-            "lloyd_frac": other["lloyd_gbs"] / HBM_PEAK_GBS,
-            "assign_avg_launch_ms": other["t_assign"] * 1e3, "assign_gbs": other["assign_gbs"],
-            "launch": other["tune"],
-            "same_passes": bool((other["passes"] == passes).all()),
-            "note": "same workload and seeds; decisions are FP64-exact in both screenings, so "
-                    "pass counts and results agree"}
+    if others:
+        out["other_screenings"] = {
+            name: {"dtype": SCREENINGS[name][1],
+                   "value": o["value"], "ms_per_step": o["elapsed"] / args.steps * 1e3,
+                   "lloyd_avg_launch_ms": o["t_lloyd"] * 1e3, "lloyd_gbs": o["lloyd_gbs"],
+                   "lloyd_frac": o["lloyd_gbs"] / HBM_PEAK_GBS,
+                   "assign_avg_launch_ms": o["t_assign"] * 1e3, "assign_gbs": o["assign_gbs"],
+                   "launch": o["tune"],
+                   "same_passes": bool((o["passes"] == passes).all()),
+                   "same_sse": o["sse"] == main_res["sse"]}
+            for name, o in others.items()}
+        out["other_screenings_note"] = ("same workload and seeds; every screening takes its "
+                                        "decisions in FP64, so pass counts and results agree")
+        out["results_identical_across_screenings"] = all(
+            v["same_passes"] and v["same_sse"] for v in out["other_screenings"].values())
     print(json.dumps(out), flush=True)
 
 

@@ -37,9 +37,10 @@
  *    the k centroids (FP64, with the per-cluster sums for Lloyd) must fit a
  *    workgroup's 160 KiB of LDS.  Largest k per padded d (8, 16, 32, 64,
  *    128) for Lloyd: 512, 462, 240, 121, 60 (FP32 screening), 512, 462, 266,
- *    134, 66 (BF16); for hpc_assign_sse: 512, 512, 400, 207, 101 (FP32),
- *    512, 512, 480, 246, 125 (BF16).  Larger combinations are refused with
- *    HPC_ERR_UNSUPPORTED before anything is launched.
+ *    134, 66 (BF16), 512, 387, 240, 121, 60 (BF16x3); for hpc_assign_sse:
+ *    512, 512, 400, 207, 101 (FP32 and BF16x3), 512, 512, 480, 246, 125
+ *    (BF16).  Larger combinations are refused with HPC_ERR_UNSUPPORTED
+ *    before anything is launched.
  */
 #ifndef HPCLUST_H
 #define HPCLUST_H
@@ -59,14 +60,22 @@ typedef enum {
 } hpc_status;
 
 /* Arithmetic that SCREENS the nearest centroid in the assignment step.  In
- * both modes the scores |c|^2 - 2 x.c are computed on the matrix cores and
+ * every mode the scores |c|^2 - 2 x.c are computed on the matrix cores and
  * the winner is accepted only when its lead over the runner-up exceeds a
  * rigorous bound on the screening error; any other point is re-decided with
  * FP64 distances.  Every decided index is therefore the one FP64 distances
  * give (lowest index on exact ties); the mode changes speed only. */
 enum {
-    HPC_PREC_FP32 = 0,     /* FP32 operands, MFMA 16x16x4 f32                  */
-    HPC_PREC_BF16_MFMA = 1 /* BF16 operands, MFMA 16x16x32 bf16, FP32 accumulate */
+    HPC_PREC_FP32 = 0,       /* FP32 operands, MFMA 16x16x4 f32                  */
+    HPC_PREC_BF16_MFMA = 1,  /* BF16 operands, MFMA 16x16x32 bf16, FP32 accumulate */
+    HPC_PREC_BF16X3_MFMA = 2 /* each operand split into BF16 high and low parts;
+                              * three MFMA 16x16x32 bf16 products per k-chunk
+                              * (hi.hi + lo.hi + hi.lo), FP32 accumulate: error
+                              * bound about 10x FP32's and 60x below BF16's at
+                              * d = 64, so few points need the FP64 re-decision,
+                              * at under a third of FP32's matrix-core time.
+                              * The centroid operand tables take twice BF16's
+                              * LDS. */
 };
 
 /* One sample of a batch.  idx_offset: first entry of this sample in the idx
@@ -150,8 +159,9 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  * the last pass at labels_out + desc[b].idx_offset.
  *   desc: HOST array of n_samples entries (validated against idx_len and
  *     c_len, the lengths of idx and C).
- *   precision: HPC_PREC_FP32 or HPC_PREC_BF16_MFMA (screening type, see
- *     above; labels, f and centroids do not depend on it).
+ *   precision: HPC_PREC_FP32, HPC_PREC_BF16_MFMA or HPC_PREC_BF16X3_MFMA
+ *     (screening type, see above; labels, f and centroids do not depend on
+ *     it).
  *   f is evaluated in FP64 from the per-cluster sums of x - r and counts (r
  *     a reference point fixed per sample): Q + sum_j (n_j |c_j - r|^2 -
  *     2 (c_j - r).S_j), Q = sum |x - r|^2, within about 1e-12 relative of

@@ -21,6 +21,7 @@ HPC_ERR_NO_MEMORY = -3
 HPC_ERR_UNSUPPORTED = -4
 PREC_FP32 = 0
 PREC_BF16_MFMA = 1
+PREC_BF16X3_MFMA = 2
 
 
 class SampleDesc(ct.Structure):

@@ -12,11 +12,11 @@ import ctypes as ct
 import numpy as np
 import torch
 
-from ._lib import PREC_BF16_MFMA, PREC_FP32, SampleDesc, Tune, check, lib
+from ._lib import PREC_BF16_MFMA, PREC_BF16X3_MFMA, PREC_FP32, SampleDesc, Tune, check, lib
 
 __all__ = [
-    "PREC_FP32", "PREC_BF16_MFMA", "SampleDesc", "make_desc", "draw_sample", "draw_samples",
-    "seed_kmeanspp", "lloyd_batch", "keep_best", "select_best", "assign_sse", "release",
+    "PREC_FP32", "PREC_BF16_MFMA", "PREC_BF16X3_MFMA", "SampleDesc", "make_desc", "draw_sample",
+    "draw_samples", "seed_kmeanspp", "lloyd_batch", "keep_best", "select_best", "assign_sse", "release",
     "version", "Plan", "Tune", "SetEncoder",
 ]
 

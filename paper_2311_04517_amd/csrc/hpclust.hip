@@ -156,16 +156,22 @@ int max_dyn_lds(int* bytes) {
     return HPC_OK;
 }
 
+bool precision_ok(int32_t p) {
+    return p == HPC_PREC_FP32 || p == HPC_PREC_BF16_MFMA || p == HPC_PREC_BF16X3_MFMA;
+}
+
 // Call f(integral_constant<int, D>, integral_constant<int, PREC>) for the
 // padded dimension D and the precision mode.
 template <class F>
 int with_dp(int D, int prec, F&& f) {
     using std::integral_constant;
-    const bool bf = prec == HPC_PREC_BF16_MFMA;
-#define HPC_DP(DD)                                                                 \
-    case DD:                                                                       \
-        return bf ? f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecBF16>{}) \
-                  : f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecF32>{})
+#define HPC_DP(DD)                                                                            \
+    case DD:                                                                                  \
+        if (prec == HPC_PREC_BF16_MFMA)                                                       \
+            return f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecBF16>{});   \
+        if (prec == HPC_PREC_BF16X3_MFMA)                                                     \
+            return f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecBF16x3>{}); \
+        return f(integral_constant<int, DD>{}, integral_constant<int, hpc::kPrecF32>{})
     switch (D) {
         HPC_DP(8);
         HPC_DP(16);
@@ -621,7 +627,7 @@ int hpc_lloyd_batch(const float* X, int64_t m, int32_t d, const int64_t* idx, in
                     kMaxD);
     if (max_iter < 1 || !(rel_tol >= 0.0) || std::isinf(rel_tol))
         return fail(HPC_ERR_INVALID_ARG, "hpc_lloyd_batch: need max_iter>=1 and finite rel_tol>=0");
-    if (precision != HPC_PREC_FP32 && precision != HPC_PREC_BF16_MFMA)
+    if (!precision_ok(precision))
         return fail(HPC_ERR_INVALID_ARG, "hpc_lloyd_batch: unknown precision %d", precision);
     int kmax = 0;
     int rc = check_desc(desc, n_samples, idx_len, c_len, d, &kmax);
@@ -659,16 +665,18 @@ int hpc_assign_sse(const float* X, int64_t m, int32_t d, const float* C, int32_t
     if (!X || !C || !sse) return fail(HPC_ERR_INVALID_ARG, "hpc_assign_sse: NULL pointer");
     if (m < 1 || !sizes_ok(d, k))
         return fail(HPC_ERR_INVALID_ARG, "hpc_assign_sse: need m>=1, 1<=d<=%d, 1<=k<=512", kMaxD);
-    if (precision != HPC_PREC_FP32 && precision != HPC_PREC_BF16_MFMA)
+    if (!precision_ok(precision))
         return fail(HPC_ERR_INVALID_ARG, "hpc_assign_sse: unknown precision %d", precision);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     Workspace* w = nullptr;
     int rc = get_ws(st, &w);
     if (rc) return rc;
-    const bool bf = precision == HPC_PREC_BF16_MFMA;
-#define HPC_ASSIGN(DD)                                                                       \
-    return bf ? launch_assign<DD, hpc::kPrecBF16>(X, m, d, C, k, labels, counts, sse, w, st) \
-              : launch_assign<DD, hpc::kPrecF32>(X, m, d, C, k, labels, counts, sse, w, st)
+#define HPC_ASSIGN(DD)                                                                         \
+    if (precision == HPC_PREC_BF16_MFMA)                                                       \
+        return launch_assign<DD, hpc::kPrecBF16>(X, m, d, C, k, labels, counts, sse, w, st);   \
+    if (precision == HPC_PREC_BF16X3_MFMA)                                                     \
+        return launch_assign<DD, hpc::kPrecBF16x3>(X, m, d, C, k, labels, counts, sse, w, st); \
+    return launch_assign<DD, hpc::kPrecF32>(X, m, d, C, k, labels, counts, sse, w, st)
     switch (pad_dim(d)) {
         case 8: HPC_ASSIGN(8);
         case 16: HPC_ASSIGN(16);
@@ -690,7 +698,7 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
                     "hpc_plan_create: need desc, 1<=d<=%d, 1<=n_samples<=65535, idx_len>=1, "
                     "c_len>=1",
                     kMaxD);
-    if (precision != HPC_PREC_FP32 && precision != HPC_PREC_BF16_MFMA)
+    if (!precision_ok(precision))
         return fail(HPC_ERR_INVALID_ARG, "hpc_plan_create: unknown precision %d", precision);
     int kmax = 0;
     int rc = check_desc(desc, n_samples, idx_len, c_len, d, &kmax);

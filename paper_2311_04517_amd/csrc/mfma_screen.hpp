@@ -3,8 +3,13 @@
 // The distance |x - c_j|^2 = |x|^2 + s_j with score s_j = |c_j|^2 - 2 x.c_j;
 // the cross term x.c_j over a tile of 16 points and blocks of 16 centroids
 // is the one dense contraction of the method and runs on MFMA:
-//   FP32 : v_mfma_f32_16x16x4_f32   (one k-slice of 4 per instruction)
-//   BF16 : v_mfma_f32_16x16x32_bf16 (32-wide k-slice, FP32 accumulation)
+//   FP32   : v_mfma_f32_16x16x4_f32   (one k-slice of 4 per instruction)
+//   BF16   : v_mfma_f32_16x16x32_bf16 (32-wide k-slice, FP32 accumulation)
+//   BF16x3 : the same instruction three times per k-slice on a two-term
+//            split of each operand, v = v_hi + v_lo (v_hi = bf16(v), v_lo =
+//            bf16(v - v_hi); v - v_hi is exact in FP32): hi.hi + lo.hi +
+//            hi.lo, leaving out lo.lo, for close to FP32 accuracy at a
+//            fraction of the FP32 matrix rate's cost
 // A = -2 c (centroids x dims), B = x^T (dims x points), the accumulator
 // starts at |c_j|^2, so the MFMA result is s_j directly.
 //
@@ -30,12 +35,20 @@
 // Certificate.  Let E(x) bound |s~_j - s_j| for the screened score, s_j the
 // exact score of the FP64 centroid; E(x) = alpha |x| cmax + beta cmax^2 with
 // (u = 2^-24, u_b = 2^-8 plus the FP32-to-BF16 double rounding)
-//   FP32 : alpha = (4d + 10) u          beta = (2d + 6) u
-//   BF16 : alpha = 4 u_b + 2 u_b^2 + (4d + 10) u (1 + u_b)^2   beta as FP32
+//   FP32   : alpha = (4d + 10) u          beta = (2d + 6) u
+//   BF16   : alpha = 4 u_b + 2 u_b^2 + (4d + 10) u (1 + u_b)^2   beta as FP32
+//   BF16x3 : alpha = 8 u_b^2 + (12d + 10) u (1 + u_b)^5          beta = (6d + 6) u
 // i.e. the rounding of the operands to the MFMA input type, plus twice the
 // classical accumulation bound of d + 1 FP32 additions (the factor two
 // leaves room for the matrix unit's internal summation order), plus the
-// rounding of |c|^2 to FP32.  The quantised key value q_j satisfies
+// rounding of |c|^2 to FP32.  For BF16x3: per coordinate the split leaves
+// |x - x_hi - x_lo| <= u_b^2 |x| and, for a = -2c rounded to FP32 first,
+// |a - a_hi - a_lo| <= (u + u_b^2 (1 + u)) |a|; with the omitted lo.lo
+// product (<= u_b^2 (1 + u_b)^2 (1 + u) |a||x|) the represented cross term
+// is off by about (3 u_b^2 + u) |a||x| (higher-order terms included, below
+// 3.03 u_b^2 |a||x|), bounded by 4 u_b^2 |a||x| (Cauchy-Schwarz over
+// coordinates, |a| = 2|c|); the accumulation is over 3d exact products
+// whose magnitudes sum to at most (1 + u)(1 + u_b)^4 |a||x|.  The quantised key value q_j satisfies
 // q_j <= v_j < q_j (1 + 2^(NB-23)), and fl() adds a relative 2^-24; h,
 // common to all j, cancels between them (its share of q_j only enlarges
 // the right-hand side of the test below).  Hence with q_1 <=
@@ -54,7 +67,7 @@ namespace hpc {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-enum : int { kPrecF32 = 0, kPrecBF16 = 1 };
+enum : int { kPrecF32 = 0, kPrecBF16 = 1, kPrecBF16x3 = 2 };
 
 template <int D>
 struct Lay {
@@ -71,7 +84,7 @@ struct Lay {
 template <int D, int PREC>
 __host__ __device__ constexpr size_t aop_bytes(int nblk) {
     return PREC == kPrecF32 ? (size_t)nblk * Lay<D>::DL * 64 * 4
-                            : (size_t)nblk * Lay<D>::KC * 64 * 16;
+                            : (size_t)nblk * Lay<D>::KC * 64 * 16 * (PREC == kPrecBF16x3 ? 2 : 1);
 }
 
 template <int PREC>
@@ -80,6 +93,11 @@ __host__ __device__ inline void screen_coeffs(int d, double* alpha, double* beta
     const double acc = (4.0 * d + 10.0) * u;
     *beta = (2.0 * d + 6.0) * u;
     *alpha = PREC == kPrecF32 ? acc : 4.0 * ub + 2.0 * ub * ub + acc * (1.0 + ub) * (1.0 + ub);
+    if (PREC == kPrecBF16x3) {
+        const double g = 1.0 + ub;
+        *beta = (6.0 * d + 6.0) * u;
+        *alpha = 8.0 * ub * ub + (12.0 * d + 10.0) * u * g * g * g * g * g;
+    }
 }
 
 // Fill the A operands (-2 c, rounded to the MFMA type; zero for padding
@@ -109,13 +127,17 @@ __device__ void build_operands(const double* __restrict__ C64, int k, int d, int
             a[e] = v;
         }
     } else {
+        // BF16x3: the low parts follow the high parts as a second table
         __bf16* a = static_cast<__bf16*>(aop);
-        for (int e = threadIdx.x; e < nblk * KC * 64 * 8; e += NT) {
+        const int n = nblk * KC * 64 * 8;
+        for (int e = threadIdx.x; e < n; e += NT) {
             const int v8 = e & 7, l = (e >> 3) & 63, kc = (e >> 9) % KC, blk = (e >> 9) / KC;
             const int j = blk * 16 + (l & 15), q = kc * 8 + v8, t = (l >> 4) * DL + q;
             float v = 0.f;
             if (q < DL && j < k && C64[j * CS] == C64[j * CS]) v = -2.f * (float)C64[j * CS + t];
-            a[e] = (__bf16)v;
+            const __bf16 hi = (__bf16)v;
+            a[e] = hi;
+            if (PREC == kPrecBF16x3) a[n + e] = (__bf16)(v - (float)hi);
         }
     }
 }
@@ -216,6 +238,25 @@ __device__ __forceinline__ void key_params(int nblk, unsigned* kmask, float* qsc
     *qscale = __builtin_ldexpf(1.0f, nb - 20);
 }
 
+// BF16x3 B operands: this lane's coordinates as x_hi = bf16(x) and x_lo =
+// bf16(x - x_hi) (the difference is exact in FP32), in the k-chunk layout
+// of the BF16 operands (zero past DL).
+template <int D>
+__device__ __forceinline__ void split_point(const float (&xq)[Lay<D>::DL],
+                                            bf16x8 (&xh)[Lay<D>::KC], bf16x8 (&xl)[Lay<D>::KC]) {
+    constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int q = kc * 8 + v;
+            const float x = q < DL ? xq[q < DL ? q : 0] : 0.f;
+            const __bf16 hi = (__bf16)x;
+            xh[kc][v] = hi;
+            xl[kc][v] = (__bf16)(x - (float)hi);
+        }
+}
+
 // Keys of this lane's point against all nblk*16 centroids; returns the
 // merged three best (identical in the point's four lanes).  h: the point's
 // shifted norm from screen_shift.
@@ -235,6 +276,24 @@ __device__ __forceinline__ Top3 screen_tile(const float (&xq)[Lay<D>::DL],
             for (int q = 0; q < DL; ++q)
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
                                                            acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
+        }
+    } else if constexpr (PREC == kPrecBF16x3) {
+        bf16x8 xh[KC], xl[KC];
+        split_point<D>(xq, xh, xl);
+        const bf16x8* a = static_cast<const bf16x8*>(aop);
+        const bf16x8* al = a + nblk * KC * 64;
+        for (int blk = 0; blk < nblk; ++blk) {
+            f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int o = (blk * KC + kc) * 64 + lane;
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[o], xh[kc], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xl[kc], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xh[kc], acc, 0, 0, 0);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
@@ -360,6 +419,18 @@ __device__ __forceinline__ void rescan_rows(const float (&xq)[Lay<D>::DL], bool 
             for (int q = 0; q < DL; ++q)
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
                                                            acc, 0, 0, 0);
+        } else if constexpr (PREC == kPrecBF16x3) {
+            bf16x8 xh[KC], xl[KC];
+            split_point<D>(xq, xh, xl);
+            const bf16x8* a = static_cast<const bf16x8*>(aop);
+            const bf16x8* al = a + nblk * KC * 64;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int o = (blk * KC + kc) * 64 + lane;
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[o], xh[kc], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xl[kc], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xh[kc], acc, 0, 0, 0);
+            }
         } else {
             const bf16x8* a = static_cast<const bf16x8*>(aop);
 #pragma unroll

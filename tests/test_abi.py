@@ -66,6 +66,8 @@ def test_lloyd_batch_validation(L):
     _err(L, call(tol=-1.0))
     _err(L, call(tol=float("nan")))
     _err(L, call(prec=7))
+    _err(L, call(prec=3))
+    _err(L, call(prec=-1))
     _err(L, call(desc=_desc((0, 0, 2, 3))))              # s < k
     _err(L, call(desc=_desc((5, 0, 10, 3))))             # idx range beyond idx_len
     _err(L, call(desc=_desc((0, 4, 10, 3))))             # centroid block beyond c_len

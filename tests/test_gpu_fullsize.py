@@ -186,16 +186,18 @@ def test_precision_set_bf16_full_size(hp, orc):
     Cb = C[desc[b].c_offset:desc[b].c_offset + k * d].view(k, d).contiguous()
     lab16, cnt16, sse16 = hp.assign_sse(X, Cb, precision=hp.PREC_BF16_MFMA)
     lab32, cnt32, sse32 = hp.assign_sse(X, Cb, precision=hp.PREC_FP32)
-    # both screenings take every decision in FP64: identical labels, counts
+    lab3, cnt3, sse3 = hp.assign_sse(X, Cb, precision=hp.PREC_BF16X3_MFMA)
+    # every screening takes each decision in FP64: identical labels, counts
     # and (same launch shape and summation order) identical SSE
     assert torch.equal(lab16, lab32) and torch.equal(cnt16, cnt32)
-    assert sse16.item() == sse32.item()
+    assert torch.equal(lab3, lab32) and torch.equal(cnt3, cnt32)
+    assert sse16.item() == sse32.item() == sse3.item()
     assert cnt16.sum().item() == m
     _check_rows(orc, X, Cb, lab16, 200_000, seed=4)
     _say(f"precision: full assign SSE {sse16.item():.6e}")
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_metric_workload_full_size(hp, orc, tmp_path, prec):
     """The benchmark's own configuration: m = 1e7, d = 32, k = 25, 1,024
     workers x s = 10,000, autotuned plan, a cold round then a warm round

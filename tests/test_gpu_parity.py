@@ -58,7 +58,7 @@ def test_draw_samples_batch_bit_exact(hp, orc):
 
 
 # ---------------------------------------------------------------- assign + SSE
-PRECS = [0, 1]  # FP32 and BF16 MFMA screening: both must decide exactly
+PRECS = [0, 1, 2]  # FP32, BF16 and BF16x3 MFMA screening: all must decide exactly
 
 
 @pytest.mark.parametrize("prec", PRECS)

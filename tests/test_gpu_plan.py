@@ -45,7 +45,7 @@ CONFIGS = [dict(), dict(wg_per_cu=1, copies=1, order=0), dict(wg_per_cu=2, copie
            dict(wg_per_cu=0, copies=2, order=1)]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_plan_lloyd_every_config_matches_oracle(hp, orc, prec):
     n, d = 40, 32
     Xn, Xg, desc, idx_len, c_len, ss, ks, sid0 = _uneven(hp, orc, n, d, seed=3)
