@@ -197,7 +197,10 @@ int hpc_select_best(const float *C_inc, const double *f_inc, int32_t n_workers, 
  *   labels (device int32[m], nullable): nearest valid centroid (lowest index
  *     on ties); counts (device int64[k], nullable): points per centroid;
  *   sse (device double[1]): sum_i min_j |x_i - c_j|^2, accumulated in FP64
- *     in a fixed order (bitwise reproducible for a fixed launch shape).
+ *     in a fixed order (bitwise reproducible for a fixed launch shape; the
+ *     shape follows from d, k, the precision and the device: 256-thread
+ *     workgroups, or 768-thread ones for d <= 64 when the centroid tables
+ *     leave more resident waves that way).
  *   precision: as in hpc_lloyd_batch; the objective is always the FP64
  *     direct-difference distance to the chosen centroid summed in FP64.
  * Errors: NULL X/C/sse, m < 1, sizes out of range, every row degenerate is

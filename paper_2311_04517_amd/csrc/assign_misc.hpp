@@ -62,9 +62,11 @@ __host__ __device__ inline size_t assign_lds_bytes(int k, int nt) {
 
 // Up to d = 32 five waves per SIMD, each with three tiles of rows in
 // flight; wider rows keep three register buffers at the occupancy their
-// registers allow.
+// registers allow.  The 768-thread form (three waves per SIMD from one
+// workgroup) is for centroid tables too large for several 256-thread
+// workgroups per CU in LDS.
 template <int D, int NT, int PREC>
-__global__ __launch_bounds__(NT, D <= 32 ? 5 : (D <= 64 ? 3 : 2)) void k_assign_sse(const float* __restrict__ X, int64_t m, int d,
+__global__ __launch_bounds__(NT, NT > 256 ? NT / 256 : (D <= 32 ? 5 : (D <= 64 ? 3 : 2))) void k_assign_sse(const float* __restrict__ X, int64_t m, int d,
                                                    const float* __restrict__ C, int k,
                                                    int32_t* __restrict__ labels,
                                                    unsigned long long* __restrict__ counts,

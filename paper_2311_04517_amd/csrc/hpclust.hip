@@ -254,26 +254,36 @@ int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, int n_wg, hipStr
     });
 }
 
-template <int D, int PREC>
-int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
-                  int64_t* counts, double* sse, Workspace* w, hipStream_t st) {
-    constexpr int NT = 256;
-    const size_t lds = hpc::assign_lds_bytes<D, PREC>(k, NT);
-    int lds_max = 0;
-    int rc = max_dyn_lds(&lds_max);
-    if (rc) return rc;
-    if (lds > (size_t)lds_max)
-        return fail(HPC_ERR_UNSUPPORTED, "k=%d, padded d=%d: centroids exceed LDS", k, D);
+// Resident waves per CU of k_assign_sse<D, NT, PREC> with `lds` bytes of
+// LDS per workgroup (0 if it does not fit); sets the attribute allowing
+// more than 64 KiB.
+template <int D, int NT, int PREC>
+int assign_waves_per_cu(size_t lds, int lds_max, int* waves) {
+    *waves = 0;
+    if (lds > (size_t)lds_max) return HPC_OK;
     auto kern = hpc::k_assign_sse<D, NT, PREC>;
     if (lds > 64 * 1024)
         HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = 0, cus = 0;
+    int per_cu = 0;
     HPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds));
-    rc = device_cus(&cus);
+    *waves = per_cu * (NT / hpc::kWave);
+    return HPC_OK;
+}
+
+template <int D, int NT, int PREC>
+int launch_assign_nt(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
+                     int64_t* counts, double* sse, Workspace* w, hipStream_t st, int waves_cu) {
+    constexpr int NW = NT / hpc::kWave;
+    const size_t lds = hpc::assign_lds_bytes<D, PREC>(k, NT);
+    int cus = 0;
+    int rc = device_cus(&cus);
     if (rc) return rc;
-    int64_t want = (m + 63) / 64;  // tiles of 16 rows per wave, 4 waves
-    int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * std::max(1, per_cu) * 4));
+    // four workgroup slots per resident workgroup (grid-stride over tiles of
+    // 16 rows per wave), at most one workgroup per NW tiles
+    const int64_t want = (m + 16 * NW - 1) / (16 * NW);
+    const int64_t slots = (int64_t)cus * std::max(1, waves_cu / NW) * 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, slots));
     rc = ws_reserve_dev(w, Carve::need({(size_t)grid * 8}));
     if (rc) return rc;
     Carve cv(w->dev);
@@ -282,12 +292,36 @@ int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32
         hipLaunchKernelGGL(hpc::k_fill_u64, dim3((k + 255) / 256), dim3(256), 0, st,
                            reinterpret_cast<unsigned long long*>(counts), (int64_t)k, 0ull);
     const bool vec = (d == D) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, X, m, d, C, k, labels,
-                       reinterpret_cast<unsigned long long*>(counts), partials, vec);
+    hipLaunchKernelGGL((hpc::k_assign_sse<D, NT, PREC>), dim3(grid), dim3(NT), lds, st, X, m, d,
+                       C, k, labels, reinterpret_cast<unsigned long long*>(counts), partials, vec);
     hipLaunchKernelGGL(hpc::k_reduce_partials<256>, dim3(1), dim3(256), 0, st, partials, grid,
                        sse);
     HPC_HIP(hipGetLastError());
     return HPC_OK;
+}
+
+// Full assignment: 256-thread workgroups, or (d <= 64) 768-thread ones when
+// the centroid tables leave room for more resident waves that way.
+template <int D, int PREC>
+int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
+                  int64_t* counts, double* sse, Workspace* w, hipStream_t st) {
+    int lds_max = 0;
+    int rc = max_dyn_lds(&lds_max);
+    if (rc) return rc;
+    int w256 = 0, w768 = 0;
+    rc = assign_waves_per_cu<D, 256, PREC>(hpc::assign_lds_bytes<D, PREC>(k, 256), lds_max, &w256);
+    if (rc) return rc;
+    if constexpr (D <= 64) {
+        rc = assign_waves_per_cu<D, 768, PREC>(hpc::assign_lds_bytes<D, PREC>(k, 768), lds_max,
+                                               &w768);
+        if (rc) return rc;
+        if (w768 > w256)
+            return launch_assign_nt<D, 768, PREC>(X, m, d, C, k, labels, counts, sse, w, st,
+                                                  w768);
+    }
+    if (w256 == 0)
+        return fail(HPC_ERR_UNSUPPORTED, "k=%d, padded d=%d: centroids exceed LDS", k, D);
+    return launch_assign_nt<D, 256, PREC>(X, m, d, C, k, labels, counts, sse, w, st, w256);
 }
 
 bool sizes_ok(int32_t d, int32_t k) { return d >= 1 && d <= kMaxD && k >= 1 && k <= 512; }
