@@ -86,7 +86,10 @@ __global__ __launch_bounds__(NT, NT > 256 ? NT / 256 : (D <= 32 ? 5 : (D <= 64 ?
     int* flag = hist + k;
     p += (((size_t)k * 8 + 15) / 16) * 16;
     double* red = reinterpret_cast<double*>(p);
-    const int tid = threadIdx.x, wid = tid / kWave, lane = tid & 63, g = lane >> 4;
+    // the wave index is made wave-uniform so that tile indices live in
+    // scalar registers
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
     for (int e = tid; e < k * CS; e += NT) {
         const int j = e / CS, t = e % CS;
         C64[e] = t < d ? (double)C[(int64_t)j * d + t] : 0.0;

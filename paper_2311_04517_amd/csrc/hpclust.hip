@@ -308,13 +308,19 @@ int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
     if (rc) return rc;
-    int w256 = 0, w768 = 0;
+    int w256 = 0, w768 = 0, w1024 = 0;
     rc = assign_waves_per_cu<D, 256, PREC>(hpc::assign_lds_bytes<D, PREC>(k, 256), lds_max, &w256);
     if (rc) return rc;
     if constexpr (D <= 64) {
         rc = assign_waves_per_cu<D, 768, PREC>(hpc::assign_lds_bytes<D, PREC>(k, 768), lds_max,
                                                &w768);
         if (rc) return rc;
+        rc = assign_waves_per_cu<D, 1024, PREC>(hpc::assign_lds_bytes<D, PREC>(k, 1024), lds_max,
+                                                &w1024);
+        if (rc) return rc;
+        if (w1024 > w256 && w1024 > w768)
+            return launch_assign_nt<D, 1024, PREC>(X, m, d, C, k, labels, counts, sse, w, st,
+                                                   w1024);
         if (w768 > w256)
             return launch_assign_nt<D, 768, PREC>(X, m, d, C, k, labels, counts, sse, w, st,
                                                   w768);
