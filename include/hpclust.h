@@ -78,6 +78,16 @@ enum {
                               * LDS. */
 };
 
+/* The screening error bound of a precision mode: for a point x and the
+ * FP64 centroids c_j of one call, every screened score s~_j satisfies
+ * |s~_j - s_j| <= alpha |x| cmax + beta cmax^2 (s_j = |c_j|^2 - 2 x.c_j
+ * exactly, cmax = max_j |c_j|); the winner is certified when the two best
+ * keys differ by more than 2.5 times that plus the key quantisation.
+ * Returns the coefficients the kernels use for dimension d (the derivation
+ * is in the header of the screening code).  Host only, no GPU needed.
+ * Errors: NULL outputs, d outside [1, 128], unknown precision. */
+int hpc_screen_bound(int32_t d, int32_t precision, double *alpha, double *beta);
+
 /* One sample of a batch.  idx_offset: first entry of this sample in the idx
  * array (and in labels_out); s: sample size; k: number of centroids;
  * c_offset: offset, in floats, of this sample's k x d block in C;

@@ -16,8 +16,8 @@ from ._lib import PREC_BF16_MFMA, PREC_BF16X3_MFMA, PREC_FP32, SampleDesc, Tune,
 
 __all__ = [
     "PREC_FP32", "PREC_BF16_MFMA", "PREC_BF16X3_MFMA", "SampleDesc", "make_desc", "draw_sample",
-    "draw_samples", "seed_kmeanspp", "lloyd_batch", "keep_best", "select_best", "assign_sse", "release",
-    "version", "Plan", "Tune", "SetEncoder",
+    "draw_samples", "seed_kmeanspp", "lloyd_batch", "keep_best", "select_best", "assign_sse",
+    "screen_bound", "release", "version", "Plan", "Tune", "SetEncoder",
 ]
 
 
@@ -143,6 +143,14 @@ def select_best(C_inc, f_inc, k: int, d: int):
     check(lib().hpc_select_best(_ptr(C_inc), _ptr(f_inc), n, k, d, _ptr(Cb), _ptr(fb), _ptr(wb),
                                 ct.c_void_p(_stream())), "hpc_select_best")
     return Cb, fb, wb
+
+
+def screen_bound(d: int, precision=PREC_FP32):
+    """(alpha, beta) of the screening error bound the kernels use for
+    dimension d: |s~ - s| <= alpha |x| cmax + beta cmax^2 (host only)."""
+    a, b = ct.c_double(), ct.c_double()
+    check(lib().hpc_screen_bound(d, precision, ct.byref(a), ct.byref(b)), "hpc_screen_bound")
+    return a.value, b.value
 
 
 def assign_sse(X, C, *, want_labels=True, want_counts=True, precision=PREC_FP32, labels=None,

@@ -699,6 +699,21 @@ int hpc_select_best(const float* C_inc, const double* f_inc, int32_t n_workers, 
     return HPC_OK;
 }
 
+int hpc_screen_bound(int32_t d, int32_t precision, double* alpha, double* beta) {
+    if (!alpha || !beta) return fail(HPC_ERR_INVALID_ARG, "hpc_screen_bound: NULL pointer");
+    if (d < 1 || d > kMaxD)
+        return fail(HPC_ERR_INVALID_ARG, "hpc_screen_bound: need 1<=d<=%d", kMaxD);
+    if (!precision_ok(precision))
+        return fail(HPC_ERR_INVALID_ARG, "hpc_screen_bound: unknown precision %d", precision);
+    if (precision == HPC_PREC_BF16_MFMA)
+        hpc::screen_coeffs<hpc::kPrecBF16>(d, alpha, beta);
+    else if (precision == HPC_PREC_BF16X3_MFMA)
+        hpc::screen_coeffs<hpc::kPrecBF16x3>(d, alpha, beta);
+    else
+        hpc::screen_coeffs<hpc::kPrecF32>(d, alpha, beta);
+    return HPC_OK;
+}
+
 int hpc_assign_sse(const float* X, int64_t m, int32_t d, const float* C, int32_t k,
                    int32_t precision, int32_t* labels, int64_t* counts, double* sse,
                    void* hip_stream) {
