@@ -180,7 +180,15 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  *   f_out (device double[n]), iters_out (device int32[n]); labels_out
  *   nullable (device int32[idx_len]).
  * Samples may be processed in any order and concurrently; each sample's
- * result depends only on its own inputs.
+ * result depends only on its own inputs.  For d > 32, when the GPU holds at
+ * least twice as many workgroups as there are samples, a sample that starts
+ * with every centroid valid and rows of X 16-byte aligned is worked by two
+ * workgroups, each on every other tile of 16 points, which exchange their
+ * partial sums once per pass (until a re-seed, the gathered copy or the
+ * direct-sum objective is needed; one workgroup finishes the sample).  The
+ * results then differ from one workgroup's only in the order of the FP64
+ * sums.  A sample whose partner workgroup does not arrive within about a
+ * second (not expected) reports f = NaN.
  * Errors: NULL required pointers, max_iter < 1, rel_tol < 0 or NaN, any
  * s < k, offsets beyond idx_len / c_len, unknown precision. */
 int hpc_lloyd_batch(const float *X, int64_t m, int32_t d, const int64_t *idx, int64_t idx_len,
@@ -250,8 +258,9 @@ typedef struct {
  * array, validated as in hpc_lloyd_batch against idx_len and c_len, copied;
  * 1 <= n_samples <= 65535) of d-dimensional data, screening precision
  * `precision`.  The plan owns its device memory (about idx_len * (4*pad(d)
- * + 44) bytes, pad(d) the next of 8, 16, 32, 64, 128) until
- * hpc_plan_destroy.  *out receives the handle (NULL on error).  The default
+ * + 44) bytes, pad(d) the next of 8, 16, 32, 64, 128, plus, where samples
+ * can be shared (hpc_lloyd_batch), n_samples * 32 * (kmax * (pad(d) + 1) +
+ * 8) bytes of exchange slots) until hpc_plan_destroy.  *out receives the handle (NULL on error).  The default
  * configuration is {0, 0, 0, 0}. */
 int hpc_plan_create(int32_t d, const hpc_sample_desc *desc, int32_t n_samples, int64_t idx_len,
                     int64_t c_len, int32_t precision, hpc_plan *out);

@@ -191,13 +191,23 @@ struct ResGeo {
     int copies = 1;      // private partial-sum copies per workgroup
     size_t lds = 0;      // dynamic LDS bytes
     int per_cu_max = 0;  // occupancy limit at this LDS size
+    int split = 1;       // 2: two workgroups per sample (shared warm samples)
 };
+
+// Doubles of the pair-exchange buffer for n samples: two halves, two pass
+// parities, and per slot the partial sums (kmax rows of D + 1) and Q.
+size_t xbuf_doubles(int n, int kmax, int D) {
+    return (size_t)n * 4 * ((size_t)kmax * (D + 1) + 8);
+}
 
 // Launch geometry for a batch of n_wg samples with at most kmax centroids.
 // copies_req 0 = as many private copies as fit in 64 KiB; wg_per_cu 0 = as
-// many workgroups per CU as the occupancy allows.
+// many workgroups per CU as the occupancy allows.  With allow_split, wide
+// rows (d > 32) and at least twice as many resident workgroups as samples,
+// every sample gets two workgroups (warm samples are then shared).
 template <int D, int PREC>
-int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo* out) {
+int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo* out,
+                      bool allow_split) {
     using S = hpc::Smem<D, kNT, PREC>;
     constexpr int NW = kNT / hpc::kWave;
     int lds_max = 0;
@@ -227,7 +237,9 @@ int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo*
     if (rc) return rc;
     per_cu = std::max(1, per_cu);
     const int use = wg_per_cu > 0 ? std::min(per_cu, wg_per_cu) : per_cu;
-    out->grid = std::max(1, std::min(n_wg, cus * use));
+    const int64_t cap = (int64_t)cus * use;
+    out->split = (allow_split && D >= 64 && 2 * (int64_t)n_wg <= cap) ? 2 : 1;
+    out->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)n_wg * out->split, cap));
     out->copies = copies;
     out->lds = lds;
     out->per_cu_max = per_cu;
@@ -238,18 +250,29 @@ int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo*
 template <int D, int PREC>
 int launch_resident(hpc::LloydArgs a, const ResGeo& g, hipStream_t st) {
     a.n_copies = g.copies;
+    a.split = g.split;
+    a.xstride = a.kmax * (D + 1) + 8;
+    if (g.split == 2 && (!a.xbuf || !a.xflag))
+        return fail(HPC_ERR_INVALID_ARG, "shared samples without an exchange buffer");
     hipLaunchKernelGGL(hpc::k_fill_i32, dim3(1), dim3(64), 0, st, a.queue, (int64_t)1, 0);
+    if (g.split == 2)
+        hipLaunchKernelGGL(hpc::k_fill_i32, dim3((4 * a.n_samples + 255) / 256), dim3(256), 0, st,
+                           a.xflag, (int64_t)4 * a.n_samples, 0);
     hipLaunchKernelGGL((hpc::k_lloyd_resident<D, kNT, PREC>), dim3(g.grid), dim3(kNT), g.lds, st,
                        a);
     HPC_HIP(hipGetLastError());
     return HPC_OK;
 }
 
-int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, int n_wg, hipStream_t st) {
+int resident_geo(int D, int prec, int kmax, int n_wg, bool allow_split, ResGeo* g) {
     return with_dp(D, prec, [&](auto Dc, auto Pc) {
-        ResGeo g;
-        int rc = resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(a.kmax, n_wg, 0, 0, &g);
-        if (rc) return rc;
+        return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(kmax, n_wg, 0, 0, g,
+                                                                           allow_split);
+    });
+}
+
+int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, const ResGeo& g, hipStream_t st) {
+    return with_dp(D, prec, [&](auto Dc, auto Pc) {
         return launch_resident<decltype(Dc)::value, decltype(Pc)::value>(a, g, st);
     });
 }
@@ -387,12 +410,17 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     int rc = get_ws(st, &w);
     if (rc) return rc;
     const int D = pad_dim(d);
+    ResGeo g;
+    rc = resident_geo(D, precision, kmax, n, !seed_only, &g);
+    if (rc) return rc;
     const std::vector<int32_t> order = longest_first(desc, n);
     const size_t desc_b = (size_t)n * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n * 4;
     const size_t sbuf_b = (size_t)idx_len * D * 4;
-    const size_t need =
-        Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 40, (size_t)idx_len * 4});
+    const size_t xbuf_b = g.split == 2 ? xbuf_doubles(n, kmax, D) * 8 : 0;
+    const size_t xflag_b = g.split == 2 ? (size_t)n * 16 : 0;
+    const size_t need = Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 40,
+                                     (size_t)idx_len * 4, xbuf_b, xflag_b});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
@@ -401,6 +429,8 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     float* sbuf = static_cast<float*>(cv.take(sbuf_b));
     double* d2 = static_cast<double*>(cv.take((size_t)idx_len * 40));
     int32_t* lbuf = static_cast<int32_t*>(cv.take((size_t)idx_len * 4));
+    double* xbuf = static_cast<double*>(cv.take(xbuf_b));
+    int32_t* xflag = static_cast<int32_t*>(cv.take(xflag_b));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
     memcpy(host.data() + desc_b, order.data(), order_b);
@@ -430,7 +460,9 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     a.call_id = call_id;
     a.chosen = chosen;
     a.vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-    return dispatch_resident(D, precision, a, n, st);
+    a.xbuf = g.split == 2 ? xbuf : nullptr;
+    a.xflag = g.split == 2 ? xflag : nullptr;
+    return dispatch_resident(D, precision, a, g, st);
 }
 
 int next_pow2(int64_t v) {
@@ -456,6 +488,8 @@ struct hpc_plan_s {
     float* sbuf = nullptr;
     double* d2 = nullptr;
     int32_t* lbuf = nullptr;
+    double* xbuf = nullptr;    // pair exchange (only when samples can be shared)
+    int32_t* xflag = nullptr;
     float* tC = nullptr;  // autotuner scratch
     double* tf = nullptr;
     int32_t* tit = nullptr;
@@ -477,11 +511,15 @@ int plan_check(hpc_plan p, const char* where) {
     return HPC_OK;
 }
 
-int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g) {
+int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g, bool allow_split) {
     return with_dp(p->D, p->prec, [&](auto Dc, auto Pc) {
-        return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(p->kmax, p->n,
-                                                                           t.wg_per_cu, t.copies, g);
+        return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(
+            p->kmax, p->n, t.wg_per_cu, t.copies, g, allow_split);
     });
+}
+
+int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g) {
+    return plan_geometry(p, t, g, p->xbuf != nullptr);
 }
 
 hpc::LloydArgs plan_args(hpc_plan p, const float* X, int64_t m, const int64_t* idx, float* C,
@@ -508,6 +546,8 @@ hpc::LloydArgs plan_args(hpc_plan p, const float* X, int64_t m, const int64_t* i
     a.kmax = p->kmax;
     a.n_cand = 3;
     a.vec4 = (p->d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    a.xbuf = p->xbuf;
+    a.xflag = p->xflag;
     return a;
 }
 
@@ -774,13 +814,21 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     };
     if (hipGetDevice(&p->device) != hipSuccess)
         return cleanup(fail(HPC_ERR_HIP, "hpc_plan_create: hipGetDevice failed"));
+    // samples can be shared only if the default geometry (the most
+    // workgroups per CU) shares them; then the exchange buffers are made
+    ResGeo g0;
+    rc = plan_geometry(p, p->tune, &g0, true);
+    if (rc) return cleanup(rc);
+    const bool shareable = g0.split == 2;
     const size_t desc_b = (size_t)n_samples * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n_samples * 8;
     const size_t sbuf_b = (size_t)idx_len * p->D * 4;
     const size_t d2_b = (size_t)idx_len * 40;  // D^2 and up to four candidate distances
+    const size_t xbuf_b = shareable ? xbuf_doubles(n_samples, kmax, p->D) * 8 : 0;
+    const size_t xflag_b = shareable ? (size_t)n_samples * 16 : 0;
     const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)idx_len * 4,
                                      (size_t)c_len * 4, (size_t)n_samples * 8,
-                                     (size_t)n_samples * 4});
+                                     (size_t)n_samples * 4, xbuf_b, xflag_b});
     hipError_t e = hipMalloc(&p->mem, need);
     if (e != hipSuccess) {
         p->mem = nullptr;
@@ -798,6 +846,10 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     p->tC = static_cast<float*>(cv.take((size_t)c_len * 4));
     p->tf = static_cast<double*>(cv.take((size_t)n_samples * 8));
     p->tit = static_cast<int32_t*>(cv.take((size_t)n_samples * 4));
+    if (shareable) {
+        p->xbuf = static_cast<double*>(cv.take(xbuf_b));
+        p->xflag = static_cast<int32_t*>(cv.take(xflag_b));
+    }
     std::vector<int32_t> orders = longest_first(desc, n_samples);
     orders.resize((size_t)2 * n_samples);
     std::iota(orders.begin() + n_samples, orders.end(), 0);

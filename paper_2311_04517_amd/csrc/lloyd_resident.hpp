@@ -67,7 +67,51 @@ struct LloydArgs {
     uint32_t call_id;
     int32_t* chosen;
     int32_t vec4;  // rows of X are 16-byte aligned (d % 4 == 0, aligned base)
+    // shared samples (d > 32): with split == 2 every sample is two queue
+    // tasks, and a warm sample read straight from X is worked by two
+    // workgroups, each on every other tile, which exchange their partial
+    // sums once per pass
+    int32_t split;
+    double* xbuf;     // per sample, half and pass parity: xstride doubles
+    int32_t* xflag;   // per sample four ints, zeroed per launch (pair_barrier)
+    int32_t xstride;  // kmax * Lay<D>::CS + 8
 };
+
+// Spin limit of a shared sample's per-pass wait for its partner (about a
+// second at the sleep below); past it the sample is abandoned with f = NaN
+// rather than waiting for ever.
+constexpr int kPairSpinLimit = 1 << 19;
+
+// A shared sample's flags (four ints, zeroed per launch): passes counted
+// by each half, and the first workgroup's decision.
+enum : int { kPairShared = 1, kPairAlone = 2 };
+
+// The first workgroup's decision for its sample, as seen by the second
+// (kPairAlone if it is not published within the spin limit).  One thread.
+__device__ inline int pair_decision(int32_t* flags) {
+    for (int spin = 0; spin < kPairSpinLimit; ++spin) {
+        const int v = __hip_atomic_load(flags + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (v != 0) return v;
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return kPairAlone;
+}
+
+// Release this workgroup's slot (every thread has stored its part and
+// passed a barrier, and fences its own stores at device scope before it),
+// count one more shared pass for `half`, and wait until the partner has
+// counted `target`.  Called by one thread; false if the partner did not
+// arrive within the spin limit.
+__device__ inline bool pair_barrier(int32_t* flags, int half, int target) {
+    __hip_atomic_fetch_add(flags + half, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    for (int spin = 0;
+         __hip_atomic_load(flags + (1 - half), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target;
+         ++spin) {
+        if (spin >= kPairSpinLimit) return false;
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
 
 // Rows of one gathered sample (stride D, zero padded).
 template <int D>
@@ -422,14 +466,21 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
     double alpha, beta;
     screen_coeffs<PREC>(d, &alpha, &beta);
 
+    // shared samples exist for the wide instantiations only: up to d = 32
+    // the kernel has no scalar or vector registers to spare for them
+    const bool two = D >= 64 && a.split == 2;
     for (;;) {
         if (tid == 0) L.ints[15] = atomicAdd(a.queue, 1);
         __syncthreads();
         // uniform across the workgroup: the sample's descriptor, sizes and
         // base pointers then live in scalar registers
-        const int slot = __builtin_amdgcn_readfirstlane(L.ints[15]);
+        const int task = __builtin_amdgcn_readfirstlane(L.ints[15]);
         __syncthreads();
-        if (slot >= a.n_samples) break;
+        if (task >= (two ? 2 * a.n_samples : a.n_samples)) break;
+        // with shared samples the two tasks of a sample are consecutive:
+        // its second task is handed out right after the first, so a
+        // workgroup never waits for a partner that no workgroup will take
+        const int slot = two ? task >> 1 : task, half = two ? task & 1 : 0;
         const int b = a.order ? a.order[slot] : slot;
         const hpc_sample_desc ds = a.desc[b];
         const int s = ds.s, k = ds.k;
@@ -478,6 +529,17 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             }
             __syncthreads();
         };
+        // the second workgroup of a sample takes no decision of its own: it
+        // waits for the first one's (the centroids it would judge by are
+        // rewritten when the first workgroup finishes a sample alone)
+        int32_t* const pflags = two ? a.xflag + 4 * slot : nullptr;
+        if (half == 1) {
+            if (tid == 0) L.ints[14] = pair_decision(pflags);
+            __syncthreads();
+            const int dec = __builtin_amdgcn_readfirstlane(L.ints[14]);
+            __syncthreads();
+            if (dec != kPairShared) continue;
+        }
         for (int e = tid; e < k * CS; e += NT) {
             const int j = e / CS, t = e % CS;
             L.C64[e] = t < d ? (double)a.C[ds.c_offset + (int64_t)j * d + t] : 0.0;
@@ -495,6 +557,17 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         };
         const bool direct_ok = !a.seed_only && a.vec4 && d == D;
         bool gathered = !direct_ok || any_degenerate();
+        // a sample is shared only while it reads its rows straight from X
+        // with every centroid valid; both workgroups take this decision
+        // (and every later one) from identical data.  (Where samples can be
+        // shared, the flags are read through readfirstlane: wave-uniform,
+        // so the tile mapping derived from them stays in scalar registers.)
+        if (two) gathered = __builtin_amdgcn_readfirstlane(gathered);
+        bool paired = two && !gathered;
+        if (two && half == 0 && tid == 0)
+            __hip_atomic_store(pflags + 2, paired ? kPairShared : kPairAlone, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (half == 1 && !paired) continue;  // (same data as the first: does not happen)
         if (gathered) gather();
 
         if (a.seed_only) {
@@ -510,6 +583,25 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             unsigned kmask;
             float qscale;
             key_params(nblk, &kmask, &qscale);
+            // the exchange slots of a shared sample: this workgroup's and its
+            // partner's, for the parity of pass p
+            auto xslot = [&](int hh, int p) {
+                return a.xbuf + (((size_t)slot * 2 + hh) * 2 + (p & 1)) * a.xstride;
+            };
+            // leaving a shared sample (a reseed, the gathered copy or the
+            // direct-sum objective is needed): the second workgroup stops;
+            // the first adds the partner's partial sums of pass p, its last
+            // exchange, to its own and continues alone.  True if this
+            // workgroup leaves.
+            auto unpair = [&](int p) {
+                paired = false;
+                if (half == 1) return true;
+                const double* th = xslot(1, p);
+                for (int e = tid; e < k * CS; e += NT) L.psum[e] += th[e];
+                __syncthreads();
+                return false;
+            };
+            bool left = false;
             for (;;) {
                 // reading rows through the indices costs more per pass than
                 // reading the gathered copy (scattered 128-byte rows against
@@ -518,8 +610,18 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // passes makes the copy, which bounds the loss to about twice
                 // the better choice made in hindsight
                 if (!gathered && it > 0 && (it >= kDirectPasses || any_degenerate())) {
+                    if (paired && unpair(it - 1)) {
+                        left = true;
+                        break;
+                    }
                     gather();
                     gathered = true;
+                }
+                // the flags are set under branches on workgroup-wide values
+                // the compiler cannot see are uniform: restate that they are
+                if (two) {
+                    gathered = __builtin_amdgcn_readfirstlane(gathered);
+                    paired = __builtin_amdgcn_readfirstlane(paired);
                 }
                 kmeanspp_wg<D, NT, PREC>(sv, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
                                          (uint64_t)it, nullptr, L);
@@ -548,6 +650,10 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 }
                 __syncthreads();
                 lds_f64* pw = as_lds(L.psum + (size_t)(wid % copies) * k * CS);
+                // tiles in pass order: a shared sample's workgroup takes every
+                // other one (tile v of this workgroup is tile 2v + half)
+                const int tsh = paired ? 1 : 0, toff = paired ? half : 0;
+                auto TI = [&](int v) { return (v << tsh) + toff; };
                 double fl = 0.0;
                 // tiles of 16 points per wave, software pipelined over three
                 // register buffers: the rows of the next two tiles are in
@@ -559,12 +665,12 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // lanes are masked in process), which keeps the memory
                 // counters exact for the compiler's wait placement
                 auto fetch = [&](int tile, float (&dst)[DL], int& old) {
-                    const int i = min(tile * 16 + pl, s - 1);
+                    const int i = min(TI(tile) * 16 + pl, s - 1);
                     load_quarter<D>(Sg + (size_t)i * D, g, dst);
                     old = lprev[(unsigned)i];
                 };
                 auto process = [&](int tile, const float (&xq)[DL], int old) {
-                    const int i = tile * 16 + pl;
+                    const int i = TI(tile) * 16 + pl;
                     const bool valid = i < s;
                     const float xn2 = point_norm2<D>(xq);
                     const float xn = cert_norm(xn2);
@@ -614,13 +720,13 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 if (gathered) {
                     fetch(wid, xa, la);
                     fetch(wid + NW, xb, lb);
-                    for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
+                    for (int tile = wid; TI(tile) * 16 < s; tile += 3 * NW) {
                         fetch(tile + 2 * NW, xc, lc);
                         process(tile, xa, la);
-                        if ((tile + NW) * 16 >= s) break;
+                        if (TI(tile + NW) * 16 >= s) break;
                         fetch(tile + 3 * NW, xa, la);
                         process(tile + NW, xb, lb);
-                        if ((tile + 2 * NW) * 16 >= s) break;
+                        if (TI(tile + 2 * NW) * 16 >= s) break;
                         fetch(tile + 4 * NW, xb, lb);
                         process(tile + 2 * NW, xc, lc);
                     }
@@ -630,7 +736,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     // on rows still in flight
                     const int64_t* ix = a.idx + ds.idx_offset;
                     auto IDX = [&](int tile) -> int64_t {
-                        return ix[(unsigned)min(tile * 16 + pl, s - 1)];
+                        return ix[(unsigned)min(TI(tile) * 16 + pl, s - 1)];
                     };
                     // an index outside [0, m) reads a row of zeros, as the
                     // gather does (a pointer select: nothing touches the
@@ -638,7 +744,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     auto ROW = [&](int tile, int64_t r, float (&dst)[DL], int& old) {
                         const float* src = (r >= 0 && r < a.m) ? a.X + r * D : g_zero_row;
                         load_quarter<D>(src, g, dst);
-                        old = lprev[(unsigned)min(tile * 16 + pl, s - 1)];
+                        old = lprev[(unsigned)min(TI(tile) * 16 + pl, s - 1)];
                     };
                     // the prologue issues its loads in the order the loop
                     // body does (the scheduling barriers stop the compiler
@@ -655,16 +761,16 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     __builtin_amdgcn_sched_barrier(0);
                     // no early exit inside the body (the loads past the end
                     // are clamped and cheap; skipped tiles are not processed)
-                    for (int tile = wid; tile * 16 < s; tile += 3 * NW) {
+                    for (int tile = wid; TI(tile) * 16 < s; tile += 3 * NW) {
                         ROW(tile + 2 * NW, ic, xc, lc);
                         ic = IDX(tile + 5 * NW);
                         process(tile, xa, la);
                         ROW(tile + 3 * NW, ia, xa, la);
                         ia = IDX(tile + 6 * NW);
-                        if ((tile + NW) * 16 < s) process(tile + NW, xb, lb);
+                        if (TI(tile + NW) * 16 < s) process(tile + NW, xb, lb);
                         ROW(tile + 4 * NW, ib, xb, lb);
                         ib = IDX(tile + 7 * NW);
-                        if ((tile + 2 * NW) * 16 < s) process(tile + 2 * NW, xc, lc);
+                        if (TI(tile + 2 * NW) * 16 < s) process(tile + 2 * NW, xc, lc);
                     }
                 }
                 // The pass objective from the sums: with S_j the sum of x - r
@@ -676,6 +782,37 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // distances are summed directly instead (which also keeps an
                 // exact zero exact).
                 __syncthreads();
+                // A shared sample's workgroups exchange their partial sums
+                // (in the first pass also their shares of Q) and each adds
+                // its own and the partner's in the same way, a + b against
+                // b + a: both then hold the same objective and centroids.
+                const double* th = nullptr;
+                if (paired) {
+                    double* mine = xslot(half, it);
+                    for (int e = tid; e < k * CS; e += NT) {
+                        double S = 0.0;
+                        for (int gg = 0; gg < copies; ++gg) S += L.psum[(size_t)gg * k * CS + e];
+                        mine[e] = S;
+                    }
+                    if (first) {
+                        fl = block_sum<NT>(fl, L.red);  // this workgroup's share of Q
+                        if (tid == 0) mine[k * CS] = fl;
+                    }
+                    __threadfence();
+                    __syncthreads();
+                    if (tid == 0) L.ints[14] = pair_barrier(pflags, half, it + 1);
+                    __syncthreads();
+                    const bool arrived = __builtin_amdgcn_readfirstlane(L.ints[14]) != 0;
+                    __threadfence();
+                    if (!arrived) {
+                        // the partner never came: abandon the sample
+                        f = __builtin_nan("");
+                        paired = false;
+                        left = half == 1;
+                        break;
+                    }
+                    th = xslot(1 - half, it);
+                }
                 double fp = 0.0;
                 for (int e = tid; e < k * CS; e += NT) {
                     const int j = e / CS, t = e % CS;
@@ -685,21 +822,33 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         S += L.psum[(size_t)gg * k * CS + e];
                         n += L.psum[(size_t)gg * k * CS + j * CS + D];
                     }
+                    if (th) {
+                        S += th[e];
+                        n += th[j * CS + D];
+                    }
                     if (n > 0.0) {
                         const double dc = L.C64[e] - L.ref[t];
                         fp = __fma_rn(dc, __fma_rn(n, dc, -2.0 * S), fp);
                     }
                 }
-                if (first) {
+                if (first && !th) {
                     double v2[2] = {fl, fp};
                     block_sum_n<NT, 2>(v2, L.red);
                     Qr = v2[0];
                     fp = v2[1];
                 } else {
                     fp = block_sum<NT>(fp, L.red);
+                    if (first) Qr = fl + th[k * CS];
                 }
                 f = Qr + fp;
                 if (!(f > kSumsObjectiveMin * Qr)) {
+                    if (paired) {
+                        if (unpair(it)) {
+                            left = true;
+                            break;
+                        }
+                        th = nullptr;
+                    }
                     const int64_t* ixs = a.idx + ds.idx_offset;
                     double fe = 0.0;
                     for (int tile = wid; tile * 16 < s; tile += NW) {
@@ -727,21 +876,28 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                         sum += L.psum[(size_t)gg * k * CS + e];
                         n += L.psum[(size_t)gg * k * CS + j * CS + D];
                     }
+                    if (th) {
+                        sum += th[e];
+                        n += th[j * CS + D];
+                    }
                     double v = 0.0;
                     if (t < d) v = n > 0.0 ? L.ref[t] + sum / n : __builtin_nan("");
                     L.C64[e] = v;
                 }
                 __syncthreads();
             }
-            if (tid == 0) {
+            // the first workgroup of a shared sample writes its results
+            if (tid == 0 && half == 0) {
                 a.f_out[b] = f;
                 a.iters_out[b] = it;
             }
+            if (__builtin_amdgcn_readfirstlane(left)) continue;
         }
-        for (int e = tid; e < k * d; e += NT) {
-            const int j = e / d, t = e % d;
-            a.C[ds.c_offset + e] = (float)L.C64[j * CS + t];
-        }
+        if (half == 0)
+            for (int e = tid; e < k * d; e += NT) {
+                const int j = e / d, t = e % d;
+                a.C[ds.c_offset + e] = (float)L.C64[j * CS + t];
+            }
         __syncthreads();
     }
 }

@@ -426,6 +426,118 @@ def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
     assert checked >= n // 2
 
 
+def _shared_case(hp, orc, Xn, n, s, k, C0, seed, prec, *, min_long=0, reseeded=(), tight=False):
+    """Warm starts at d = 64 (a padded width with samples shared by two
+    workgroups when few samples are run) against the oracle, and against
+    the same starts on a misaligned X (rows gathered: never shared)."""
+    m, d = Xn.shape
+    flat = torch.zeros(m * d + 1, dtype=torch.float32, device="cuda")
+    flat[1:] = torch.from_numpy(Xn.ravel()).cuda()
+    Xmis = flat[1:].view(m, d)
+    Xal = torch.from_numpy(Xn).cuda()
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=seed, sample_id=np.arange(n), d=d)
+    idx = hp.draw_samples(m, desc, idx_len)
+    idx_n = idx.cpu().numpy()
+    outs = []
+    for Xg in (Xal, Xmis):
+        C = torch.from_numpy(C0.ravel().copy()).cuda()
+        f, it, lab = hp.lloyd_batch(Xg, idx, desc, C, want_labels=True, precision=prec)
+        outs.append((C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()))
+    (Cg, fg, itg, lg), (Cm, fm, itm, lm) = outs
+    assert np.isfinite(fg).all()
+    # shared and unshared runs differ only in the order the sums are added
+    assert np.array_equal(itg, itm) and np.array_equal(lg, lm)
+    assert np.allclose(fg, fm, rtol=1e-11, atol=0) and np.allclose(Cg, Cm, rtol=1e-6, atol=1e-6)
+    assert itg.max() >= min_long
+    checked = 0
+    for b in range(n):
+        ib = idx_n[b * s:(b + 1) * s]
+        ro = orc.lloyd(Xn, ib, k, C0[b].astype(np.float64), seed=seed, sample_id=b,
+                       want_margins=True)
+        if b in reseeded:
+            assert ro.diag["n_seed_calls"] >= 1
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        assert itg[b] == ro.iters and rel(fg[b], ro.f) <= F_REL, (b, itg[b], ro.iters)
+        assert_centroids(Cg[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, Xn[ib])
+        assert_labels(lg[b * s:(b + 1) * s], ro.labels, ro.margins)
+    assert checked >= n // 2
+    return fg, itg
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_shared_samples_converge_like_the_oracle(hp, orc, prec):
+    """Few warm samples at d = 64 are each worked by two workgroups that
+    exchange their partial sums every pass; from good starts they stay
+    shared until they converge."""
+    m, d, n, s, k = 60_000, 64, 6, 4000, 10
+    mx = synthetic.gaussian_mixture(m, d, k, seed=64, centre_box=10.0, std=1.0)
+    Xn, centres = mx.X.numpy(), mx.centres.numpy()
+    rng = np.random.default_rng(3)
+    C0 = np.stack([centres + rng.normal(0, 0.5, (k, d)) for _ in range(n)]).astype(np.float32)
+    _shared_case(hp, orc, Xn, n, s, k, C0, 5, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_shared_samples_long_runs_and_reseed(hp, orc, prec):
+    """Uniform data at d = 64: runs from random starts outlast the
+    direct-read passes, and a centroid far from every point empties in the
+    first pass; both end the sharing (the second workgroup stops, the first
+    takes over its partial sums and continues alone)."""
+    m, d, n, s, k = 40_000, 64, 6, 3000, 12
+    Xn = torch.rand(m, d, generator=torch.Generator().manual_seed(33)).numpy()
+    rng = np.random.default_rng(8)
+    C0 = Xn[rng.integers(0, m, size=(n, k))].astype(np.float32)
+    C0[1, 3] = 1e4
+    C0[4, 0] = -1e4
+    _shared_case(hp, orc, Xn, n, s, k, C0, 6, prec, min_long=16, reseeded=(1, 4))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_shared_samples_tight_clusters(hp, orc, prec):
+    """Tight clusters at d = 64: the objective falls below 1% of the
+    scatter, the pass sums the points' distances directly, and the sharing
+    ends there."""
+    m, d, n, s, k = 40_000, 64, 4, 3000, 8
+    mx = synthetic.gaussian_mixture(m, d, k, seed=12, centre_box=20.0, std=0.05)
+    Xn, centres = mx.X.numpy(), mx.centres.numpy()
+    rng = np.random.default_rng(2)
+    C0 = np.stack([centres + rng.normal(0, 0.02, (k, d)) for _ in range(n)]).astype(np.float32)
+    _shared_case(hp, orc, Xn, n, s, k, C0, 7, prec)
+
+
+def test_shared_samples_in_a_plan_round(hp, orc):
+    """The batch-plan path with shared samples (d = 64, warm round from
+    incumbents): every worker agrees with the oracle."""
+    m, d, n, s, k = 60_000, 64, 8, 4000, 10
+    Xn, Xg = _mix(m, d, 10, seed=65, box=10.0, std=1.0)
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=9, sample_id=np.arange(n), d=d)
+    rng = np.random.default_rng(4)
+    C_inc0 = Xn[rng.integers(0, m, size=n * k)].astype(np.float32).ravel()
+    with hp.Plan(d, desc, idx_len, c_len, precision=hp.PREC_BF16X3_MFMA) as plan:
+        idx = torch.empty(idx_len, dtype=torch.int64, device="cuda")
+        C = torch.empty(c_len, device="cuda")
+        C_inc = torch.from_numpy(C_inc0.copy()).cuda()
+        f_inc = torch.full((n,), float("inf"), dtype=torch.float64, device="cuda")
+        f = torch.empty(n, dtype=torch.float64, device="cuda")
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        plan.round(X=Xg, idx=idx, C=C, C_inc=C_inc, f_inc=f_inc, f_out=f, iters_out=it)
+        torch.cuda.synchronize()
+        idx_n, Cg, fg, itg = idx.cpu().numpy(), C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy()
+    checked = 0
+    for b in range(n):
+        ib = idx_n[b * s:(b + 1) * s]
+        ro = orc.lloyd(Xn, ib, k, C_inc0[b * k * d:(b + 1) * k * d].reshape(k, d).astype(np.float64),
+                       seed=9, sample_id=b)
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        assert itg[b] == ro.iters and rel(fg[b], ro.f) <= F_REL
+        assert_centroids(Cg[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, Xn[ib])
+    assert checked >= n // 2
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_lloyd_tight_clusters_sum_the_objective_directly(hp, orc, prec):
     """Tight clusters far apart: the objective is a tiny fraction of the
