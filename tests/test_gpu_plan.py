@@ -82,13 +82,16 @@ def test_plan_lloyd_every_config_matches_oracle(hp, orc, prec):
                     assert itg[b] == ref[0][b] and rel(fg[b], ref[1][b]) <= 1e-12
 
 
-def test_plan_round_graph_replays_match_eager_and_oracle(hp, orc):
+@pytest.mark.parametrize("d", [16, 64])
+def test_plan_round_graph_replays_match_eager_and_oracle(hp, orc, d):
     """One worker-loop round (draw, start from incumbent, Lloyd, keep-best,
     advance sample ids) captured once and replayed round after round, with
     the program's own work and synchronisations in between: every replay
     equals the same round run eagerly, and each round equals the oracle
-    started from the incumbents the GPU held before it."""
-    n, d, rounds = 24, 16, 4
+    started from the incumbents the GPU held before it.  At d = 64 the warm
+    rounds share their samples between two workgroups (the captured
+    sequence zeroes the exchange flags with a fill kernel)."""
+    n, rounds = 24, 4
     Xn, Xg, desc, idx_len, c_len, ss, ks, sid0 = _uneven(hp, orc, n, d, seed=5, s_hi=3000)
     dn = _dn(desc)
     m = Xn.shape[0]
