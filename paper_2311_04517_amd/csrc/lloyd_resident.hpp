@@ -6,11 +6,15 @@
 // Section 6.5), and the K-means passes (Algorithm 1) with the stop rule of
 // Section 6.5.  A persistent grid pulls samples from a queue in
 // longest-first order, so hundreds of samples of uneven size share one
-// launch with no inter-workgroup synchronisation at all.
+// launch.  When samples are few (at least twice as many resident
+// workgroups as samples, d > 32), each sample is two queue tasks and a warm
+// sample is worked by both workgroups, each on every other tile, with one
+// exchange of partial sums per pass (see the pass loop); otherwise there is
+// no inter-workgroup synchronisation at all.
 //
 // Arithmetic: the assignment screens all centroids on the matrix cores
-// (FP32 or BF16 MFMA, mfma_screen.hpp) and certifies the winner with a
-// rigorous error bound; the rare point that is not certified is re-decided
+// (FP32, BF16 or BF16x3 MFMA, mfma_screen.hpp) and certifies the winner
+// with a rigorous error bound; a point that is not certified is re-decided
 // in FP64.  The distance that enters the
 // objective, the K-means++ weights D^2, the potentials, the centroid sums
 // and the centroids themselves are FP64.  Every index the method decides is
@@ -20,7 +24,8 @@
 // D floats, zero padded) that stays hot in L2/MALL across passes; centroids
 // sit in LDS as FP64 plus the MFMA A operands (-2c) and |c|^2; per-wave FP64
 // partial sums of the update live in LDS; D^2 lives in scratch, each element
-// owned by one thread.
+// owned by one thread.  Warm samples read their rows straight from X through
+// their indices until a gathered copy pays (kDirectPasses).
 #pragma once
 
 #include "common.hpp"
