@@ -353,6 +353,30 @@ def test_crowded_centroids_are_rescanned_exactly(hp, orc, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_far_from_the_origin(hp, orc, prec):
+    """Clusters 10^4 from the origin: |x|^2 dominates every key, so the key
+    quantisation and the error bound leave most points uncertified and the
+    FP64 pair decision and row rescan take them; labels, counts and the
+    SSE still match the oracle, in the assignment and in a Lloyd pass."""
+    rng = np.random.default_rng(21)
+    d, k, m = 32, 20, 20_000
+    G = rng.normal(0, 3.0, size=(k, d)) + 1.0e4
+    Xn = (G[rng.integers(0, k, size=m)] + rng.normal(0, 1.0, size=(m, d))).astype(np.float32)
+    Cn = (G + rng.normal(0, 0.3, size=(k, d))).astype(np.float32)
+    Xg = torch.from_numpy(Xn).cuda()
+    lab, cnt, sse = hp.assign_sse(Xg, torch.from_numpy(Cn).cuda(), precision=prec)
+    o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
+    lg = lab.cpu().numpy()
+    assert_labels(lg, o["labels"], o["margins"])
+    assert np.array_equal(cnt.cpu().numpy(), np.bincount(lg, minlength=k))
+    assert rel(sse.item(), o["sse"]) <= SSE_REL
+    idx = np.arange(m, dtype=np.int64)
+    desc, _, _ = hp.make_desc([m], [k], seed=3, sample_id=[0], d=d)
+    Cg, fg, itg, lg2 = _lloyd_gpu(hp, Xg, idx, desc, Cn, max_iter=1, precision=prec)
+    assert_labels(lg2, o["labels"], o["margins"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_direct_and_gathered_rows_agree(hp, orc, prec):
     """Rows read straight from X through the indices (d equal to the padded
     width, aligned X) and rows gathered into scratch (misaligned X) give
@@ -467,11 +491,12 @@ def _shared_case(hp, orc, Xn, n, s, k, C0, seed, prec, *, min_long=0, reseeded=(
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_shared_samples_converge_like_the_oracle(hp, orc, prec):
-    """Few warm samples at d = 64 are each worked by two workgroups that
-    exchange their partial sums every pass; from good starts they stay
+@pytest.mark.parametrize("d", [64, 128])
+def test_shared_samples_converge_like_the_oracle(hp, orc, prec, d):
+    """Few warm samples at d = 64 and 128 are each worked by two workgroups
+    that exchange their partial sums every pass; from good starts they stay
     shared until they converge."""
-    m, d, n, s, k = 60_000, 64, 6, 4000, 10
+    m, n, s, k = 60_000, 6, 4000, 10
     mx = synthetic.gaussian_mixture(m, d, k, seed=64, centre_box=10.0, std=1.0)
     Xn, centres = mx.X.numpy(), mx.centres.numpy()
     rng = np.random.default_rng(3)
