@@ -532,6 +532,46 @@ def test_shared_samples_tight_clusters(hp, orc, prec):
     _shared_case(hp, orc, Xn, n, s, k, C0, 7, prec)
 
 
+def test_shared_and_unshared_samples_in_one_launch(hp, orc):
+    """One launch at d = 64 with uneven samples: warm ones are shared by two
+    workgroups, while samples with degenerate rows (cold, or partly seeded)
+    are run by their first workgroup alone after it tells the second so;
+    every sample agrees with the oracle."""
+    m, d, n = 60_000, 64, 10
+    mx = synthetic.gaussian_mixture(m, d, 12, seed=66, centre_box=10.0, std=1.0)
+    Xn, Xg = mx.X.numpy(), mx.X.cuda()
+    rng = np.random.default_rng(6)
+    ss = rng.integers(600, 4000, size=n)
+    ks = rng.integers(4, 16, size=n)
+    desc, idx_len, c_len = hp.make_desc(ss, ks, seed=11, sample_id=np.arange(n), d=d)
+    idx = hp.draw_samples(m, desc, idx_len)
+    idx_n = idx.cpu().numpy()
+    dn = _desc_np(desc)
+    C0 = np.zeros(c_len, dtype=np.float64)
+    for b in range(n):
+        co, k = dn["c_offset"][b], dn["k"][b]
+        rows = Xn[rng.integers(0, m, size=k)].astype(np.float64)
+        if b % 3 == 0:
+            rows[:] = np.nan  # cold
+        elif b % 3 == 1:
+            rows[::2] = np.nan  # partly seeded
+        C0[co:co + k * d] = rows.ravel()
+    Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx_n, desc, C0.astype(np.float32))
+    checked = 0
+    for b in range(n):
+        io, s, k, co = dn["idx_offset"][b], dn["s"][b], dn["k"][b], dn["c_offset"][b]
+        ib = idx_n[io:io + s]
+        ro = orc.lloyd(Xn, ib, k, C0[co:co + k * d].reshape(k, d), seed=11, sample_id=b,
+                       want_margins=True)
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        assert itg[b] == ro.iters and rel(fg[b], ro.f) <= F_REL, (b, itg[b], ro.iters)
+        assert_centroids(Cg[co:co + k * d].reshape(k, d), ro.C, Xn[ib])
+        assert_labels(lg[io:io + s], ro.labels, ro.margins)
+    assert checked >= n // 2
+
+
 def test_shared_samples_in_a_plan_round(hp, orc):
     """The batch-plan path with shared samples (d = 64, warm round from
     incumbents): every worker agrees with the oracle."""
