@@ -92,8 +92,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
-                                   "supported (samples would shard across GPUs, see DESIGN.md)",
+        print(json.dumps({"error": "runs on one GPU only: running on several GPUs (samples "
+                                   "sharded across GPUs, one process each) is not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import numpy as np

@@ -56,7 +56,7 @@ typedef enum {
     HPC_ERR_INVALID_ARG = -1, /* bad pointer, size, offset or option          */
     HPC_ERR_HIP = -2,         /* a HIP runtime call failed                     */
     HPC_ERR_NO_MEMORY = -3,   /* scratch allocation failed                     */
-    HPC_ERR_UNSUPPORTED = -4  /* valid request outside what this build handles */
+    HPC_ERR_UNSUPPORTED = -4  /* valid request outside what the library handles */
 } hpc_status;
 
 /* Arithmetic that SCREENS the nearest centroid in the assignment step.  In
