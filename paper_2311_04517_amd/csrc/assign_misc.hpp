@@ -95,30 +95,27 @@ __global__ __launch_bounds__(NT, NT > 256 ? NT / 256 : (D <= 32 ? 5 : (D <= 64 ?
         C64[e] = t < d ? (double)C[(int64_t)j * d + t] : 0.0;
     }
     for (int j = tid; j < k; j += NT) hist[j] = 0;
+    unsigned long long* const mx2 = reinterpret_cast<unsigned long long*>(red + NW);
     if (tid == 0) {
-        int nv = 0;
-        double mx = 0.0;
-        for (int j = 0; j < k; ++j) {
-            const float c0 = C[(int64_t)j * d];
-            if (c0 != c0) continue;
-            ++nv;
-            double n2 = 0.0;
-            for (int t = 0; t < d; ++t) {
-                const double v = (double)C[(int64_t)j * d + t];
-                n2 = __fma_rn(v, v, n2);
-            }
-            mx = n2 > mx ? n2 : mx;
-        }
-        flag[0] = nv;
-        reinterpret_cast<double*>(red)[NW] = sqrt(mx);
+        flag[0] = 0;
+        *mx2 = 0ull;
     }
     __syncthreads();
+    // valid rows and the largest squared norm, one row per thread (the
+    // norms are >= 0, so their bit patterns order as unsigned integers)
+    for (int j = tid; j < k; j += NT) {
+        if (C64[j * CS] != C64[j * CS]) continue;
+        double n2 = 0.0;
+        for (int t = 0; t < d; ++t) n2 = __fma_rn(C64[j * CS + t], C64[j * CS + t], n2);
+        atomicAdd(&flag[0], 1);
+        atomicMax(mx2, (unsigned long long)__double_as_longlong(n2));
+    }
     build_operands<D, PREC, NT>(C64, k, d, nblk, aop, nrm);
     __syncthreads();
     const int n_valid = flag[0];
     double alpha, beta;
     screen_coeffs<PREC>(d, &alpha, &beta);
-    const double cmax = red[NW];
+    const double cmax = sqrt(__longlong_as_double((long long)*mx2));
     const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
     unsigned kmask;
     float qscale;

@@ -205,6 +205,21 @@ __device__ __forceinline__ void block_sum_n(double (&v)[NV], double* red) {
     __syncthreads();
 }
 
+// Whether v holds on any thread of the workgroup (every thread gets the
+// answer).  Two barriers; the first NT / 64 ints of `slots` are scratch.
+template <int NT>
+__device__ __forceinline__ bool block_any(bool v, int* slots) {
+    constexpr int NW = NT / kWave;
+    const bool w = __ballot(v) != 0ull;
+    if ((threadIdx.x & (kWave - 1)) == 0) slots[threadIdx.x / kWave] = w ? 1 : 0;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r |= slots[i];
+    __syncthreads();
+    return r != 0;
+}
+
 // Copy sample row i (FP32, padded) into an FP64 centroid row.
 template <int D, int NT>
 __device__ __forceinline__ void set_row_from_sample(double* dst64, const SampleView<D>& sv, int i) {
@@ -474,8 +489,13 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
     // shared samples exist for the wide instantiations only: up to d = 32
     // the kernel has no scalar or vector registers to spare for them
     const bool two = D >= 64 && a.split == 2;
+    // every workgroup's first task is its own index (no atomic on one
+    // address from the whole grid at once); later ones come from the queue
+    bool first_task = true;
     for (;;) {
-        if (tid == 0) L.ints[15] = atomicAdd(a.queue, 1);
+        if (tid == 0)
+            L.ints[15] = first_task ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(a.queue, 1);
+        first_task = false;
         __syncthreads();
         // uniform across the workgroup: the sample's descriptor, sizes and
         // base pointers then live in scalar registers
@@ -558,7 +578,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         auto any_degenerate = [&]() {
             int deg = 0;
             for (int j = tid; j < k; j += NT) deg |= L.C64[j * CS] != L.C64[j * CS];
-            return __syncthreads_or(deg) != 0;
+            return block_any<NT>(deg != 0, reinterpret_cast<int*>(L.red));
         };
         const bool direct_ok = !a.seed_only && a.vec4 && d == D;
         bool gathered = !direct_ok || any_degenerate();
@@ -614,7 +634,8 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // copy's cost): a sample still running after kDirectPasses
                 // passes makes the copy, which bounds the loss to about twice
                 // the better choice made in hindsight
-                if (!gathered && it > 0 && (it >= kDirectPasses || any_degenerate())) {
+                const bool deg = __builtin_amdgcn_readfirstlane(any_degenerate());
+                if (!gathered && it > 0 && (it >= kDirectPasses || deg)) {
                     if (paired && unpair(it - 1)) {
                         left = true;
                         break;
@@ -628,8 +649,9 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     gathered = __builtin_amdgcn_readfirstlane(gathered);
                     paired = __builtin_amdgcn_readfirstlane(paired);
                 }
-                kmeanspp_wg<D, NT, PREC>(sv, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
-                                         (uint64_t)it, nullptr, L);
+                if (deg)
+                    kmeanspp_wg<D, NT, PREC>(sv, s, k, 3, d2, ds.seed, kTagReseed, ds.sample_id,
+                                             (uint64_t)it, nullptr, L);
                 const double cmax = centroid_max_norm<D, NT, PREC>(L, k, d);
                 const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
                 build_operands<D, PREC, NT>(L.C64, k, d, nblk, L.aop, L.nrm);
