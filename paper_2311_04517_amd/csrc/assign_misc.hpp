@@ -153,9 +153,18 @@ __global__ __launch_bounds__(NT, NT > 256 ? NT / 256 : (D <= 32 ? 5 : (D <= 64 ?
         // end are skipped by wave-uniform guards rather than exits from the
         // unrolled body
         auto fetch = [&](int64_t tile, float (&dst)[DL]) {
-            int64_t i = tile * 16 + (lane & 15);
-            i = i < m ? i : m - 1;
-            load_quarter<D>(X + i * D, g, dst);
+            const int64_t r0 = tile * 16;  // wave-uniform
+            const float* src;
+            if (r0 + 16 <= m) {
+                // a full tile: the row base is scalar, the lane's offset a
+                // 32-bit constant
+                src = X + r0 * D + (lane & 15) * D;
+            } else {
+                int64_t i = r0 + (lane & 15);
+                i = i < m ? i : m - 1;
+                src = X + i * D;
+            }
+            load_quarter<D>(src, g, dst);
         };
         if constexpr (D <= 32) {
             float xa[DL], xb[DL], xc[DL], xd[DL];
