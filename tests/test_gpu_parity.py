@@ -91,6 +91,18 @@ def test_assign_sse_small_and_ragged(hp, orc, prec):
         assert rel(sse.item(), o["sse"]) <= SSE_REL or (o["sse"] == 0 and sse.item() == 0)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_assign_sse_no_valid_centroid(hp, prec):
+    """Every centroid degenerate: labels -1, no counts and SSE = +inf (the
+    documented result), from a grid of many workgroups."""
+    Xn, Xg = _mix(50_001, 16, 4, seed=2)
+    C = torch.full((7, 16), float("nan"), device="cuda")
+    lab, cnt, sse = hp.assign_sse(Xg, C, precision=prec)
+    assert (lab.cpu().numpy() == -1).all()
+    assert (cnt.cpu().numpy() == 0).all()
+    assert sse.item() == float("inf")
+
+
 def test_assign_sse_deterministic(hp):
     Xn, Xg = _mix(200_000, 32, 10, seed=1)
     C = Xg[:25].clone()
