@@ -129,6 +129,7 @@ struct SampleView {
 template <int D, int NT, int PREC>
 struct Smem {
     static constexpr int NW = NT / kWave;
+    static_assert(NW <= 16, "the per-wave flags of block_any take ints[16, 16 + NW)");
     double* C64;   // kmax rows of FP64 centroids, stride Lay<D>::CS
     void* aop;     // MFMA A operands, nblk x ... (see mfma_screen.hpp)
     float* nrm;    // nblk*16 score biases |c|^2
@@ -140,7 +141,7 @@ struct Smem {
     double* red;   // 4 x NW wave partials
     double* cn;    // kmax squared centroid norms
     int* deg;      // kmax degenerate-row list
-    int* ints;     // 16 scalars
+    int* ints;     // 32 scalars; [16, 16 + NW) are block_any's per-wave flags
 
     static __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
     static __host__ __device__ int nblk_of(int kmax) { return (kmax + 15) / 16; }
@@ -155,7 +156,7 @@ struct Smem {
         b += 4 * D * 8 + D * 8;
         b += union_bytes(kmax, copies);
         b += 4 * NW * 8 + align_up((size_t)kmax * 8, 16);
-        b += align_up((size_t)kmax * 4, 16) + 16 * 4;
+        b += align_up((size_t)kmax * 4, 16) + 32 * 4;
         return b;
     }
     __device__ Smem(char* base, int kmax, int copies) {
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         auto any_degenerate = [&]() {
             int deg = 0;
             for (int j = tid; j < k; j += NT) deg |= L.C64[j * CS] != L.C64[j * CS];
-            return block_any<NT>(deg != 0, reinterpret_cast<int*>(L.red));
+            return block_any<NT>(deg != 0, L.ints + 16);
         };
         const bool direct_ok = !a.seed_only && a.vec4 && d == D;
         bool gathered = !direct_ok || any_degenerate();
