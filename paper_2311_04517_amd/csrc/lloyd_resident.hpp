@@ -239,8 +239,8 @@ __device__ __forceinline__ void set_row_from_sample(double* dst64, const SampleV
 // (mfma_screen.hpp), so a distance is four partial FP64 sums and two
 // shuffles.  Weights D^2 of chunk w are read and written by wave w only.
 // The inverse-CDF search locates the chunk from the chunk totals, then the
-// owning wave scans its tiles in index order with a 16-lane FP64 prefix
-// scan, so the prefix order is the sample's index order.  chosen
+// owning wave scans its tiles in index order, four per step, each with a
+// 16-lane FP64 prefix scan, so the prefix order is the sample's index order.  chosen
 // (nullable, global) receives the picked sample-local indices.  Seeded rows
 // are written to C64.
 // ---------------------------------------------------------------------------
@@ -345,22 +345,32 @@ __device__ void kmeanspp_wg(const SampleView<D>& sv, int s, int k, int n_cand,
             for (int t = 0; t < 4; ++t) {
                 const double target = unit_double(w.w[t]) * W;
                 if (t < n_cand && c_lo <= target && target < c_hi) {  // wave-uniform
+                    // four tiles per step, one per group of 16 lanes; the
+                    // running total passes the tiles in index order, one
+                    // addition per tile, so every comparison is the one a
+                    // tile-by-tile walk makes
                     double run = c_lo;
                     int found = -1;
-                    for (int b0 = lo; b0 < hi && found < 0; b0 += 16) {
-                        const int i = b0 + p;
+                    for (int b0 = lo; b0 < hi && found < 0; b0 += 64) {
+                        const int i = b0 + 16 * g + p;
                         double v = i < hi ? d2[i] : 0.0;
 #pragma unroll
                         for (int o = 1; o < 16; o <<= 1) {
                             const double u = __shfl_up(v, o, 16);
                             if (p >= o) v += u;
                         }
-                        const bool hit = i < hi && run + v > target;
-                        const unsigned long long m16 = __ballot(hit) & 0xFFFFull;
-                        if (m16)
-                            found = b0 + __ffsll(m16) - 1;
+                        double acc = run, rg = run;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            if (q == g) rg = acc;
+                            acc += __shfl(v, 16 * q + 15);
+                        }
+                        const bool hit = i < hi && rg + v > target;
+                        const unsigned long long mk = __ballot(hit);
+                        if (mk)
+                            found = b0 + __ffsll(mk) - 1;  // lane 16 g + p is point b0 + 16 g + p
                         else
-                            run += __shfl(v, 15, 16);
+                            run = acc;
                     }
                     if (found < 0) {  // rounding: last point of positive weight in the chunk
                         for (int b0 = (hi - 1 - lo) / 16 * 16 + lo; b0 >= lo && found < 0; b0 -= 16) {
