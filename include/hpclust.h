@@ -33,6 +33,9 @@
  *  - Scratch.  The library keeps a grow-only scratch workspace per device
  *    and stream, allocated on first use (hipMalloc) and freed by
  *    hpc_release().  Calls on different streams may run concurrently.
+ *  - Sample indices.  An index outside [0, m) is not an error: that point
+ *    reads as a row of zeros (every kernel that reads rows through indices
+ *    substitutes the zero row instead of reading out of bounds).
  *  - Supported sizes: 1 <= d <= 128, 1 <= k <= 512, k <= s, m < 2^62, and
  *    the k centroids (FP64, with the per-cluster sums for Lloyd) must fit a
  *    workgroup's 160 KiB of LDS.  Largest k per padded d (8, 16, 32, 64,
@@ -168,7 +171,9 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  * f_out[b] = f, iters_out[b] = it, and (labels_out non-NULL) the labels of
  * the last pass at labels_out + desc[b].idx_offset.
  *   desc: HOST array of n_samples entries (validated against idx_len and
- *     c_len, the lengths of idx and C).
+ *     c_len, the lengths of idx and C), copied to the device through one of
+ *     eight pinned staging slots per stream: the call does not wait for
+ *     the GPU unless eight earlier uploads on the stream are still queued.
  *   precision: HPC_PREC_FP32, HPC_PREC_BF16_MFMA or HPC_PREC_BF16X3_MFMA
  *     (screening type, see above; labels, f and centroids do not depend on
  *     it).
@@ -188,7 +193,8 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  * direct-sum objective is needed; one workgroup finishes the sample).  The
  * results then differ from one workgroup's only in the order of the FP64
  * sums.  A sample whose partner workgroup does not arrive within about a
- * second (not expected) reports f = NaN.
+ * second (not expected: the grid is sized to be resident at once) is
+ * abandoned and reports f = NaN and iters_out = -1.
  * Errors: NULL required pointers, max_iter < 1, rel_tol < 0 or NaN, any
  * s < k, offsets beyond idx_len / c_len, unknown precision. */
 int hpc_lloyd_batch(const float *X, int64_t m, int32_t d, const int64_t *idx, int64_t idx_len,

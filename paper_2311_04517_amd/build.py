@@ -43,11 +43,26 @@ def source_digest() -> str:
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    cmd = [HIPCC, *FLAGS, *(extra or []), *SOURCES, "-o", OUT + ".tmp"]
+    """Compile every translation unit (in parallel, each its own device code
+    object) and link the shared library."""
+    objs = [os.path.join(CSRC, os.path.basename(s) + ".o") for s in SOURCES]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs = []
+    for src, obj in zip(SOURCES, objs):
+        cmd = [HIPCC, *compile_flags, *(extra or []), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp"]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(OUT + ".tmp", OUT)
+    for obj in objs:
+        os.remove(obj)
     return OUT
 
 

@@ -55,14 +55,24 @@ int pad_dim(int d) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Grow-only device scratch plus a pinned host staging area for descriptor
-// uploads, one per (device, stream).
+// Pinned host slots through which descriptor tables reach the device: a
+// slot is refilled only after the copy out of it has run, so an upload
+// waits on the host only when every slot's copy is still queued.
+constexpr int kStageSlots = 8;
+
+struct StageSlot {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t copied = nullptr;  // the copy out of this slot
+};
+
+// Grow-only device scratch plus the pinned staging slots, one per (device,
+// stream).
 struct Workspace {
     void* dev = nullptr;
     size_t dev_cap = 0;
-    void* pinned = nullptr;
-    size_t pinned_cap = 0;
-    hipEvent_t staged = nullptr;  // last copy out of the pinned area
+    StageSlot stage[kStageSlots];
+    int next_slot = 0;
     hipStream_t stream = nullptr;
     int device = 0;
 };
@@ -80,7 +90,7 @@ int get_ws(hipStream_t stream, Workspace** out) {
         Workspace* w = new Workspace();
         w->stream = stream;
         w->device = dev;
-        HPC_HIP(hipEventCreateWithFlags(&w->staged, hipEventDisableTiming));
+        for (auto& sl : w->stage) HPC_HIP(hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming));
         it = g_ws.emplace(key, w).first;
     }
     *out = it->second;
@@ -109,20 +119,28 @@ int ws_reserve_dev(Workspace* w, size_t bytes) {
     return HPC_OK;
 }
 
-// Copy `bytes` of host data to device scratch at `dst` on the stream via the
-// pinned staging area (waits for the previous staged copy to have run).
+// Copy `bytes` of host data to device scratch at `dst` on the stream through
+// the next pinned slot.  The host waits only if that slot's previous copy
+// has not run yet (more than kStageSlots uploads queued on the stream).
 int ws_upload(Workspace* w, void* dst, const void* src, size_t bytes) {
-    HPC_HIP(hipEventSynchronize(w->staged));
-    if (bytes > w->pinned_cap) {
-        if (w->pinned) HPC_HIP(hipHostFree(w->pinned));
-        w->pinned = nullptr;
-        size_t cap = align_up(std::max(bytes, (size_t)4096), 4096);
-        HPC_HIP(hipHostMalloc(&w->pinned, cap, hipHostMallocDefault));
-        w->pinned_cap = cap;
+    StageSlot& sl = w->stage[w->next_slot];
+    w->next_slot = (w->next_slot + 1) % kStageSlots;
+    const hipError_t q = hipEventQuery(sl.copied);
+    if (q == hipErrorNotReady)
+        HPC_HIP(hipEventSynchronize(sl.copied));
+    else if (q != hipSuccess)
+        return fail(HPC_ERR_HIP, "hipEventQuery failed: %s", hipGetErrorString(q));
+    if (bytes > sl.cap) {
+        if (sl.host) HPC_HIP(hipHostFree(sl.host));
+        sl.host = nullptr;
+        sl.cap = 0;
+        const size_t cap = align_up(std::max(bytes, (size_t)4096), 4096);
+        HPC_HIP(hipHostMalloc(&sl.host, cap, hipHostMallocDefault));
+        sl.cap = cap;
     }
-    memcpy(w->pinned, src, bytes);
-    HPC_HIP(hipMemcpyAsync(dst, w->pinned, bytes, hipMemcpyHostToDevice, w->stream));
-    HPC_HIP(hipEventRecord(w->staged, w->stream));
+    memcpy(sl.host, src, bytes);
+    HPC_HIP(hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, w->stream));
+    HPC_HIP(hipEventRecord(sl.copied, w->stream));
     return HPC_OK;
 }
 
@@ -294,9 +312,19 @@ int assign_waves_per_cu(size_t lds, int lds_max, int* waves) {
     return HPC_OK;
 }
 
+// Where the assignment's per-workgroup partial sums go: the calling
+// stream's workspace (grown as needed), or a fixed device buffer of `cap`
+// doubles (the no-allocation entry point), which then bounds the grid.
+struct PartialsDst {
+    Workspace* ws = nullptr;
+    double* fixed = nullptr;
+    int64_t cap = 0;
+};
+
 template <int D, int NT, int PREC>
 int launch_assign_nt(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
-                     int64_t* counts, double* sse, Workspace* w, hipStream_t st, int waves_cu) {
+                     int64_t* counts, double* sse, const PartialsDst& pd, hipStream_t st,
+                     int waves_cu) {
     constexpr int NW = NT / hpc::kWave;
     const size_t lds = hpc::assign_lds_bytes<D, PREC>(k, NT);
     int cus = 0;
@@ -306,11 +334,18 @@ int launch_assign_nt(const float* X, int64_t m, int d, const float* C, int k, in
     // 16 rows per wave), at most one workgroup per NW tiles
     const int64_t want = (m + 16 * NW - 1) / (16 * NW);
     const int64_t slots = (int64_t)cus * std::max(1, waves_cu / NW) * 4;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, slots));
-    rc = ws_reserve_dev(w, Carve::need({(size_t)grid * 8}));
-    if (rc) return rc;
-    Carve cv(w->dev);
-    double* partials = static_cast<double*>(cv.take((size_t)grid * 8));
+    int64_t g64 = std::max<int64_t>(1, std::min<int64_t>(want, slots));
+    double* partials = nullptr;
+    if (pd.ws) {
+        rc = ws_reserve_dev(pd.ws, Carve::need({(size_t)g64 * 8}));
+        if (rc) return rc;
+        Carve cv(pd.ws->dev);
+        partials = static_cast<double*>(cv.take((size_t)g64 * 8));
+    } else {
+        g64 = std::min<int64_t>(g64, pd.cap);
+        partials = pd.fixed;
+    }
+    const int grid = (int)g64;
     if (counts)
         hipLaunchKernelGGL(hpc::k_fill_u64, dim3((k + 255) / 256), dim3(256), 0, st,
                            reinterpret_cast<unsigned long long*>(counts), (int64_t)k, 0ull);
@@ -327,7 +362,7 @@ int launch_assign_nt(const float* X, int64_t m, int d, const float* C, int k, in
 // the centroid tables leave room for more resident waves that way.
 template <int D, int PREC>
 int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
-                  int64_t* counts, double* sse, Workspace* w, hipStream_t st) {
+                  int64_t* counts, double* sse, const PartialsDst& w, hipStream_t st) {
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
     if (rc) return rc;
@@ -601,7 +636,38 @@ int plan_enqueue_round(hpc_plan p, const float* X, int64_t m, int64_t* idx, floa
     return HPC_OK;
 }
 
+int assign_args_ok(const char* where, const float* X, int64_t m, int32_t d, const float* C,
+                   int32_t k, int32_t precision, const double* sse) {
+    if (!X || !C || !sse) return fail(HPC_ERR_INVALID_ARG, "%s: NULL pointer", where);
+    if (m < 1 || !sizes_ok(d, k))
+        return fail(HPC_ERR_INVALID_ARG, "%s: need m>=1, 1<=d<=%d, 1<=k<=512", where, kMaxD);
+    if (!precision_ok(precision))
+        return fail(HPC_ERR_INVALID_ARG, "%s: unknown precision %d", where, precision);
+    return HPC_OK;
+}
+
+int dispatch_assign(const float* X, int64_t m, int32_t d, const float* C, int32_t k,
+                    int32_t precision, int32_t* labels, int64_t* counts, double* sse,
+                    const PartialsDst& pd, hipStream_t st) {
+#define HPC_ASSIGN(DD)                                                                          \
+    if (precision == HPC_PREC_BF16_MFMA)                                                        \
+        return launch_assign<DD, hpc::kPrecBF16>(X, m, d, C, k, labels, counts, sse, pd, st);   \
+    if (precision == HPC_PREC_BF16X3_MFMA)                                                      \
+        return launch_assign<DD, hpc::kPrecBF16x3>(X, m, d, C, k, labels, counts, sse, pd, st); \
+    return launch_assign<DD, hpc::kPrecF32>(X, m, d, C, k, labels, counts, sse, pd, st)
+    switch (pad_dim(d)) {
+        case 8: HPC_ASSIGN(8);
+        case 16: HPC_ASSIGN(16);
+        case 32: HPC_ASSIGN(32);
+        case 64: HPC_ASSIGN(64);
+        case 128: HPC_ASSIGN(128);
+    }
+#undef HPC_ASSIGN
+    return fail(HPC_ERR_UNSUPPORTED, "assignment: d=%d", d);
+}
+
 }  // namespace
+
 
 extern "C" {
 
@@ -624,8 +690,10 @@ int hpc_release(void) {
         HPC_HIP(hipSetDevice(w->device));
         HPC_HIP(hipStreamSynchronize(w->stream));
         if (w->dev) HPC_HIP(hipFree(w->dev));
-        if (w->pinned) HPC_HIP(hipHostFree(w->pinned));
-        if (w->staged) HPC_HIP(hipEventDestroy(w->staged));
+        for (auto& sl : w->stage) {
+            if (sl.host) HPC_HIP(hipHostFree(sl.host));
+            if (sl.copied) HPC_HIP(hipEventDestroy(sl.copied));
+        }
         delete w;
     }
     g_ws.clear();
@@ -757,31 +825,15 @@ int hpc_screen_bound(int32_t d, int32_t precision, double* alpha, double* beta) 
 int hpc_assign_sse(const float* X, int64_t m, int32_t d, const float* C, int32_t k,
                    int32_t precision, int32_t* labels, int64_t* counts, double* sse,
                    void* hip_stream) {
-    if (!X || !C || !sse) return fail(HPC_ERR_INVALID_ARG, "hpc_assign_sse: NULL pointer");
-    if (m < 1 || !sizes_ok(d, k))
-        return fail(HPC_ERR_INVALID_ARG, "hpc_assign_sse: need m>=1, 1<=d<=%d, 1<=k<=512", kMaxD);
-    if (!precision_ok(precision))
-        return fail(HPC_ERR_INVALID_ARG, "hpc_assign_sse: unknown precision %d", precision);
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    Workspace* w = nullptr;
-    int rc = get_ws(st, &w);
+    int rc = assign_args_ok("hpc_assign_sse", X, m, d, C, k, precision, sse);
     if (rc) return rc;
-#define HPC_ASSIGN(DD)                                                                         \
-    if (precision == HPC_PREC_BF16_MFMA)                                                       \
-        return launch_assign<DD, hpc::kPrecBF16>(X, m, d, C, k, labels, counts, sse, w, st);   \
-    if (precision == HPC_PREC_BF16X3_MFMA)                                                     \
-        return launch_assign<DD, hpc::kPrecBF16x3>(X, m, d, C, k, labels, counts, sse, w, st); \
-    return launch_assign<DD, hpc::kPrecF32>(X, m, d, C, k, labels, counts, sse, w, st)
-    switch (pad_dim(d)) {
-        case 8: HPC_ASSIGN(8);
-        case 16: HPC_ASSIGN(16);
-        case 32: HPC_ASSIGN(32);
-        case 64: HPC_ASSIGN(64);
-        case 128: HPC_ASSIGN(128);
-    }
-#undef HPC_ASSIGN
-    return fail(HPC_ERR_UNSUPPORTED, "hpc_assign_sse: d=%d", d);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    PartialsDst pd;
+    rc = get_ws(st, &pd.ws);
+    if (rc) return rc;
+    return dispatch_assign(X, m, d, C, k, precision, labels, counts, sse, pd, st);
 }
+
 
 int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, int64_t idx_len,
                     int64_t c_len, int32_t precision, hpc_plan* out) {

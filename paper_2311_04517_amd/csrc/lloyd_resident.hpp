@@ -844,7 +844,9 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                     __threadfence();
                     if (!arrived) {
                         // the partner never came: abandon the sample
+                        // (f = NaN, passes = -1)
                         f = __builtin_nan("");
+                        it = -1;
                         paired = false;
                         left = half == 1;
                         break;

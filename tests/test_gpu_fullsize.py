@@ -7,7 +7,7 @@ data rows -- and properties that hold at any size cover the rest.
 Workloads (recipes in the synthetic module):
   plain batched  m = 10^7, d = 16, k in {5, 10, 25}, 256 samples of 20,000
   uneven         m = 2*10^7, d = 32, 1,024 samples, s in [1e3, 1e5], k in [2, 50]
-  precision      m = 10^8, d = 64, k = 100, 128 samples of 50,000, BF16 screening
+  precision      m = 10^8, d = 64, k = 100, 128 samples of 50,000, all three screenings
 """
 import numpy as np
 import pytest
@@ -39,10 +39,13 @@ def _dn(desc, rows):
                 seed=[desc[b].seed for b in rows], sample_id=[desc[b].sample_id for b in rows])
 
 
-def _check_samples(orc, X, idx, desc, rows, C_start, Cg, fg, itg, d, m, seed):
+def _check_samples(orc, X, idx, desc, rows, C_start, Cg, fg, itg, d, m, seed, compared=None):
     """Oracle runs of the chosen samples on their own rows (the sample's
     points in draw order), compared where the oracle reports no decision
-    within rounding of its threshold.  Returns the number compared."""
+    within rounding of its threshold.  Returns the number compared (and
+    lists the compared samples in ``compared``)."""
+    if compared is None:
+        compared = []
     sub_idx, subs, offs = [], [], []
     off = 0
     for b in rows:
@@ -61,6 +64,7 @@ def _check_samples(orc, X, idx, desc, rows, C_start, Cg, fg, itg, d, m, seed):
                  sample_id=dn["sample_id"])
     ro = orc.lloyd_batch(Xs, np.arange(len(Xs)), odesc, Co, n_threads=min(16, len(rows)))
     n = 0
+    compared.clear()
     for q, b in enumerate(rows):
         ds = desc[b]
         S = Xs[offs[q]:offs[q] + ds.s]
@@ -69,6 +73,7 @@ def _check_samples(orc, X, idx, desc, rows, C_start, Cg, fg, itg, d, m, seed):
         if not diag_clean(ro["diag"][q]):
             continue
         n += 1
+        compared.append(b)
         assert itg[b] == ro["iters"][q], (b, itg[b], ro["iters"][q])
         assert rel(fg[b], ro["f"][q]) <= F_REL
         assert_centroids(cg, Co[co[q]:co[q] + ds.k * d].reshape(ds.k, d), S)
@@ -151,22 +156,48 @@ def test_uneven_batch_one_captured_launch(hp, orc, tmp_path):
     fg, itg, Cg = f_out.cpu().numpy(), it_out.cpu().numpy(), C.cpu().numpy()
     assert ((itg >= 1) & (itg <= 300)).all() and np.isfinite(fg).all() and np.isfinite(Cg).all()
     assert torch.equal(f_inc, f_out)  # first round: every sample becomes its worker's incumbent
+    # the six smallest, the median and the two largest samples by work s*k
+    # (the largest, s near 1e5 and k near 50, set the length of the batch)
     work = ss * ks
-    pick = [int(i) for i in np.argsort(work)[:6]] + [int(np.argsort(work)[n // 2])]
-    nc = _check_samples(orc, X, idx, desc, pick, np.full(c_len, np.nan), Cg, fg, itg, d, m, 3)
-    assert nc >= 4
+    srt = np.argsort(work)
+    largest = [int(i) for i in srt[-2:]]
+    pick = [int(i) for i in srt[:6]] + [int(srt[n // 2])] + largest
+    _say(f"uneven: comparing samples {pick} (s, k of the largest: "
+         f"{[(int(ss[i]), int(ks[i])) for i in largest]})")
+    done = []
+    nc = _check_samples(orc, X, idx, desc, pick, np.full(c_len, np.nan), Cg, fg, itg, d, m, 3,
+                        compared=done)
+    _say(f"uneven: {nc} of {len(pick)} samples compared with the oracle")
+    assert nc >= 7
+    assert any(b in done for b in largest), "neither of the largest samples was compared"
     plan.close()
 
 
-def test_precision_set_bf16_full_size(hp, orc):
+@pytest.fixture(scope="module")
+def precision_data():
     mx = synthetic.precision_set(device="cuda")
     X = mx.X
-    m, d = X.shape
     del mx
     _say(f"precision set generated: {tuple(X.shape)}")
+    yield X
+    del X
+    torch.cuda.empty_cache()
+
+
+PREC_RUNS = {}
+
+
+@pytest.mark.parametrize("prec", [2, 1, 0])
+def test_precision_set_lloyd_full_size(hp, orc, precision_data, prec):
+    """A cold batch of the precision workload (128 samples of 50,000, k =
+    100, d = 64) in each screening (BF16x3 first: the workload's default):
+    both sampled workers against the oracle, and identical pass counts,
+    objectives and centroids across the screenings."""
+    X = precision_data
+    m, d = X.shape
     s, k, W = 50_000, 100, 128
     desc, idx_len, c_len = hp.make_desc([s] * W, [k] * W, seed=4, sample_id=np.arange(W), d=d)
-    with hp.Plan(d, desc, idx_len, c_len, precision=hp.PREC_BF16_MFMA) as plan:
+    with hp.Plan(d, desc, idx_len, c_len, precision=prec) as plan:
         idx = torch.empty(idx_len, dtype=torch.int64, device="cuda")
         plan.draw(m, idx)
         C = torch.full((c_len,), float("nan"), device="cuda")
@@ -175,15 +206,31 @@ def test_precision_set_bf16_full_size(hp, orc):
         f, it, _ = plan.lloyd(X, idx, C)
         e1.record()
         torch.cuda.synchronize()
-        _say(f"precision: cold batch in {e0.elapsed_time(e1):.1f} ms, passes {it.sum().item()}")
+        _say(f"precision {prec}: cold batch in {e0.elapsed_time(e1):.1f} ms, "
+             f"passes {it.sum().item()}")
         Cg, fg, itg = C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy()
         assert ((itg >= 1) & (itg <= 300)).all() and np.isfinite(fg).all()
         nc = _check_samples(orc, X, idx, desc, [0, 101], np.full(c_len, np.nan), Cg, fg, itg, d,
                             m, 4)
-        _say(f"precision: {nc} of 2 samples compared with the oracle")
-        assert nc >= 1
+        _say(f"precision {prec}: {nc} of 2 samples compared with the oracle")
+        assert nc == 2
+    PREC_RUNS[prec] = (Cg, fg, itg)
+    for other, (Co, fo, ito) in PREC_RUNS.items():
+        # every screening decides in FP64: same passes; objectives and
+        # centroids agree up to the order of the FP64 sums
+        assert np.array_equal(itg, ito), (prec, other)
+        assert np.allclose(fg, fo, rtol=1e-11, atol=0)
+        assert np.allclose(Cg, Co, rtol=1e-6, atol=1e-5)
+
+
+def test_precision_set_assign_full_size(hp, orc, precision_data):
+    X = precision_data
+    m, d = X.shape
+    k = 100
+    assert PREC_RUNS, "runs after the Lloyd test"
+    Cg, fg, _ = next(iter(PREC_RUNS.values()))
     b = int(np.argmin(fg))
-    Cb = C[desc[b].c_offset:desc[b].c_offset + k * d].view(k, d).contiguous()
+    Cb = torch.from_numpy(Cg[b * k * d:(b + 1) * k * d].reshape(k, d).copy()).cuda()
     lab16, cnt16, sse16 = hp.assign_sse(X, Cb, precision=hp.PREC_BF16_MFMA)
     lab32, cnt32, sse32 = hp.assign_sse(X, Cb, precision=hp.PREC_FP32)
     lab3, cnt3, sse3 = hp.assign_sse(X, Cb, precision=hp.PREC_BF16X3_MFMA)
@@ -193,8 +240,8 @@ def test_precision_set_bf16_full_size(hp, orc):
     assert torch.equal(lab3, lab32) and torch.equal(cnt3, cnt32)
     assert sse16.item() == sse32.item() == sse3.item()
     assert cnt16.sum().item() == m
-    _check_rows(orc, X, Cb, lab16, 200_000, seed=4)
-    _say(f"precision: full assign SSE {sse16.item():.6e}")
+    _check_rows(orc, X, Cb, lab3, 200_000, seed=4)
+    _say(f"precision: full assign SSE {sse3.item():.6e}")
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])

@@ -141,15 +141,18 @@ def test_seed_kmeanspp_bit_exact(hp, orc, d, s, k):
 def test_seed_kmeanspp_partial_and_candidates(hp, orc):
     Xn, Xg = _mix(20_000, 16, 8, seed=7)
     rng = np.random.default_rng(0)
+    clean = 0
     for n_cand in (1, 2, 3, 4):
         Cin = Xn[rng.integers(0, 20_000, size=9)].astype(np.float64)
         Cin[[1, 4, 8]] = np.nan
         Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 1500, 9, 11, 2, n_cand, Cin, n_cand)
+        assert (chg[[0, 2, 3, 5, 6, 7]] == -1).all()
         if g["min_draw_margin"] < CLEAN_MARGIN or g["min_cand_margin"] < CLEAN_MARGIN:
             continue
+        clean += 1
         assert np.array_equal(chg, cho)
-        assert (chg[[0, 2, 3, 5, 6, 7]] == -1).all()
         assert np.array_equal(Cg.astype(np.float64), Co)
+    assert clean >= 3, f"only {clean} of 4 candidate counts compared"
 
 
 def test_seed_zero_weight_and_duplicates(hp, orc):
@@ -163,8 +166,9 @@ def test_seed_zero_weight_and_duplicates(hp, orc):
     # k = s distinct points: every point chosen once
     Xn, Xg = _mix(1000, 3, 2, seed=3)
     Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 64, 64, 2, 0, 0)
-    if g["min_draw_margin"] >= CLEAN_MARGIN and g["min_cand_margin"] >= CLEAN_MARGIN:
-        assert np.array_equal(chg, cho)
+    assert g["min_draw_margin"] >= CLEAN_MARGIN and g["min_cand_margin"] >= CLEAN_MARGIN
+    assert np.array_equal(chg, cho)
+    assert len(set(chg.tolist())) == 64  # every point chosen once
 
 
 # ---------------------------------------------------------------- Lloyd
@@ -228,10 +232,10 @@ def test_lloyd_reseeds_emptied_cluster(hp, orc):
     assert ro.diag["n_seed_calls"] >= 1
     desc, _, _ = hp.make_desc([s], [k], seed=8, sample_id=[4], d=6)
     Cg, fg, itg, lg = _lloyd_gpu(hp, Xg, idx, desc, C0)
-    if diag_clean(ro.diag):
-        assert itg[0] == ro.iters and rel(fg[0], ro.f) <= F_REL
-        assert_centroids(Cg.reshape(k, 6), ro.C, Xn[idx])
-        assert_labels(lg, ro.labels, ro.margins)
+    assert diag_clean(ro.diag), "the re-seed case must be compared"
+    assert itg[0] == ro.iters and rel(fg[0], ro.f) <= F_REL
+    assert_centroids(Cg.reshape(k, 6), ro.C, Xn[idx])
+    assert_labels(lg, ro.labels, ro.margins)
 
 
 def test_lloyd_degenerate_cases(hp, orc):

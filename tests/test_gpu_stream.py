@@ -55,10 +55,14 @@ def test_stream_equals_resident_rounds(hp, orc, strategy):
     assert torch.allclose(state.C_inc, res.state.C_inc, rtol=1e-6, atol=1e-6)
     assert torch.allclose(state.f_inc, res.state.f_inc, rtol=1e-12, atol=0)
     assert all(b >= a for a, b in zip(res.t_rounds, res.t_rounds[1:]))
-    # a streamed cold sample against the oracle
-    for w in (0, 17):
+    # streamed cold samples against the oracle
+    checked = 0
+    for w in (0, 5, 17, 31):
         S = Xn[w * s:(w + 1) * s]
         ro = orc.lloyd(S, np.arange(s), k, seed=seed, sample_id=w)
-        if diag_clean(ro.diag):
-            assert res.iters_rounds[0][w] == ro.iters
-            assert rel(res.f_rounds[0][w], ro.f) <= F_REL
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        assert res.iters_rounds[0][w] == ro.iters
+        assert rel(res.f_rounds[0][w], ro.f) <= F_REL
+    assert checked >= 3, f"only {checked} of 4 streamed samples compared"
