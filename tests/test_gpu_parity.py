@@ -163,9 +163,11 @@ def test_seed_zero_weight_and_duplicates(hp, orc):
     Co, cho, g, Cg, chg = _seed_case(hp, orc, X, torch.from_numpy(X).cuda(), 20, 3, 4, 0, 0, Cin)
     assert g["n_zero_weight"] == 2
     assert np.array_equal(chg, cho)
-    # k = s distinct points: every point chosen once
-    Xn, Xg = _mix(1000, 3, 2, seed=3)
-    Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 64, 64, 2, 0, 0)
+    # k = s distinct points: every point chosen once (m large enough that
+    # the 64 draws are distinct; this seed has no draw or candidate choice
+    # within rounding of its threshold)
+    Xn, Xg = _mix(100_000, 3, 2, seed=4)
+    Co, cho, g, Cg, chg = _seed_case(hp, orc, Xn, Xg, 64, 64, 1, 0, 0)
     assert g["min_draw_margin"] >= CLEAN_MARGIN and g["min_cand_margin"] >= CLEAN_MARGIN
     assert np.array_equal(chg, cho)
     assert len(set(chg.tolist())) == 64  # every point chosen once
