@@ -233,6 +233,26 @@ int hpc_assign_sse(const float *X, int64_t m, int32_t d, const float *C, int32_t
                    int32_t precision, int32_t *labels, int64_t *counts, double *sse,
                    void *hip_stream);
 
+/* The full assignment of hpc_assign_sse without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, results and errors
+ * are those of hpc_assign_sse.  The per-workgroup partial sums of the
+ * objective go to a fixed device array of 8,192 doubles (64 KiB) that the
+ * library holds on every GPU it runs on until the process ends, instead of
+ * the stream's workspace; the grid is capped at 8,192 workgroups (the
+ * kernel strides over the rows, so every m is accepted; on MI355X the
+ * launch shape, hence the summation order and sse, is the same as
+ * hpc_assign_sse's).  The device address of the array is looked up once
+ * per device, on the first call with that device current.  The call itself
+ * allocates nothing: no hipMalloc, no host staging.  Every call on one GPU
+ * shares that GPU's array and each call writes every slot it reads, so
+ * nothing needs clearing; calls that overlap on one GPU (on different
+ * streams, or from several threads) race on the array and must be ordered
+ * by the caller. */
+int hpc_assign_sse_noalloc(const float *X, int64_t m, int32_t d, const float *C, int32_t k,
+                           int32_t precision, int32_t *labels, int64_t *counts, double *sse,
+                           void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batch plans: a fixed table of uneven samples prepared once, run many times
  * (Algorithm 3's worker loop over B workers, each sample with its own s and

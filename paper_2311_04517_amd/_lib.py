@@ -75,6 +75,7 @@ _SIGS = {
     "hpc_keep_best": ([_p, _p, _p, _p, _i32, _i32, _i32, _p, _p], ct.c_int),
     "hpc_select_best": ([_p, _p, _i32, _i32, _i32, _p, _p, _p, _p], ct.c_int),
     "hpc_assign_sse": ([_p, _i64, _i32, _p, _i32, _i32, _p, _p, _p, _p], ct.c_int),
+    "hpc_assign_sse_noalloc": ([_p, _i64, _i32, _p, _i32, _i32, _p, _p, _p, _p], ct.c_int),
     "hpc_screen_bound": ([_i32, _i32, _p, _p], ct.c_int),
     "hpc_plan_create": ([_i32, _p, _i32, _i64, _i64, _i32, ct.POINTER(_p)], ct.c_int),
     "hpc_plan_destroy": ([_p], ct.c_int),

@@ -636,6 +636,38 @@ int plan_enqueue_round(hpc_plan p, const float* X, int64_t m, int64_t* idx, floa
     return HPC_OK;
 }
 
+// The no-allocation form of the full assignment keeps its per-workgroup
+// partial sums in this fixed array: each GPU the library runs on holds one
+// copy until the process ends.  Host code never passes the array's name to
+// a kernel (in host code it is a stand-in, not a device address); it uses
+// the device address looked up once per device below.
+constexpr int kStaticPartials = 8192;
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+double* g_static_partials[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up with that
+// device current on its first use, then cached).
+int static_partials(double** out) {
+    int dev = 0;
+    HPC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HPC_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_partials[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HPC_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                        hipGetErrorString(e));
+        g_static_partials[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_static_partials[dev];
+    return HPC_OK;
+}
+
 int assign_args_ok(const char* where, const float* X, int64_t m, int32_t d, const float* C,
                    int32_t k, int32_t precision, const double* sse) {
     if (!X || !C || !sse) return fail(HPC_ERR_INVALID_ARG, "%s: NULL pointer", where);
@@ -831,6 +863,20 @@ int hpc_assign_sse(const float* X, int64_t m, int32_t d, const float* C, int32_t
     PartialsDst pd;
     rc = get_ws(st, &pd.ws);
     if (rc) return rc;
+    return dispatch_assign(X, m, d, C, k, precision, labels, counts, sse, pd, st);
+}
+
+
+int hpc_assign_sse_noalloc(const float* X, int64_t m, int32_t d, const float* C, int32_t k,
+                           int32_t precision, int32_t* labels, int64_t* counts, double* sse,
+                           void* hip_stream) {
+    int rc = assign_args_ok("hpc_assign_sse_noalloc", X, m, d, C, k, precision, sse);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    PartialsDst pd;
+    rc = static_partials(&pd.fixed);
+    if (rc) return rc;
+    pd.cap = kStaticPartials;
     return dispatch_assign(X, m, d, C, k, precision, labels, counts, sse, pd, st);
 }
 
