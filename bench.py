@@ -78,10 +78,16 @@ def parse():
                     help="run one launch of each kernel for counter collection (a 1 GiB "
                          "calibration copy, a cold batch, a warm 3-pass batch, one full "
                          "assignment) and exit")
+    ap.add_argument("--no-precision-leg", dest="precision_leg", action="store_false",
+                    help="skip the precision workload's leg of the default (metric) run")
+    ap.add_argument("--precision-m", type=int, default=None,
+                    help="rows of the precision leg's data (default 1e8)")
+    ap.add_argument("--precision-steps", type=int, default=3,
+                    help="timed steps of the precision leg")
+    ap.add_argument("--no-error-report", dest="error_report", action="store_false",
+                    help="skip the comparison of an untimed round with the oracle")
     a = ap.parse_args()
-    dflt = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="bf16"),
-            "precision": dict(m=100_000_000, workers=128, s=50_000, k=100, precision="bf16x3")}
-    for key, v in dflt[a.workload].items():
+    for key, v in WORKLOADS[a.workload].items():
         if getattr(a, key) is None:
             setattr(a, key, v)
     if a.workload == "precision":
@@ -96,25 +102,14 @@ def main():
                                    "sharded across GPUs, one process each) is not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    import synthetic
     from paper_2311_04517_amd import api
 
-    dev = "cuda"
     torch.cuda.init()
     print(f"[bench] {api.version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr,
           flush=True)
-    t_gen = time.perf_counter()
-    if args.workload == "precision":
-        mx = synthetic.precision_set(m=args.m, device=dev)
-    else:
-        mx = synthetic.metric_set(m=args.m, device=dev)
-    X = mx.X
-    torch.cuda.synchronize()
-    print(f"[bench] data {tuple(X.shape)} generated in {time.perf_counter() - t_gen:.1f}s",
-          file=sys.stderr, flush=True)
+    X = make_data(args)
     m, d = X.shape
     W, s, k = args.workers, args.s, args.k
     prec = SCREENINGS[args.precision][0]
@@ -123,34 +118,88 @@ def main():
         return
 
     copy = copy_bandwidth()
+    out, main_res = measure(api, X, args, copy, other_precision=args.other_precision)
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(X, main_res["C_before"], main_res["r_first_timed"], args, m, d, W, s,
+                           k)
+    out["cpu_baseline"] = cpu
+    if args.tts:
+        f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
+        out["time_to_sse"] = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
+    if args.workload == "metric" and args.precision_leg:
+        # the precision workload (m = 1e8, d = 64, k = 100, 128 workers of
+        # 50,000, BF16x3) in the same run: its MFMA and HBM rooflines and its
+        # error against the oracle
+        del X
+        torch.cuda.empty_cache()
+        pargs = argparse.Namespace(**vars(args))
+        pargs.workload = "precision"
+        for key, v in WORKLOADS["precision"].items():
+            setattr(pargs, key, v)
+        pargs.m = args.precision_m or WORKLOADS["precision"]["m"]
+        pargs.steps, pargs.warmup = args.precision_steps, 1
+        Xp = make_data(pargs)
+        pout, _ = measure(api, Xp, pargs, copy, other_precision=False)
+        out["precision_workload"] = pout
+        del Xp
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
+WORKLOADS = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="bf16"),
+             "precision": dict(m=100_000_000, workers=128, s=50_000, k=100, precision="bf16x3")}
+
+
+def make_data(args):
+    import torch
+
+    import synthetic
+
+    t_gen = time.perf_counter()
+    if args.workload == "precision":
+        mx = synthetic.precision_set(m=args.m, device="cuda")
+    else:
+        mx = synthetic.metric_set(m=args.m, device="cuda")
+    X = mx.X
+    del mx
+    torch.cuda.synchronize()
+    print(f"[bench] {args.workload} data {tuple(X.shape)} generated in "
+          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    return X
+
+
+def measure(api, X, args, copy, other_precision):
+    """The timed competitive rounds of one workload with its default
+    screening (and optionally the other two), the kernels' rooflines, the
+    cold round, one cold sample's latency, and the error against the oracle
+    of an untimed round."""
+    m, d = X.shape
+    W, s, k = args.workers, args.s, args.k
+    prec = SCREENINGS[args.precision][0]
+    args.error_workers = [0, W // 2] if args.error_report else None
     main_res = run_metric(api, X, args, prec)
     others = {}
-    if args.other_precision:
+    if other_precision:
         for name, (code, _, _) in SCREENINGS.items():
             if name != args.precision:
-                others[name] = run_metric(api, X, args, code)
+                a2 = argparse.Namespace(**vars(args))
+                a2.error_workers = None
+                others[name] = run_metric(api, X, a2, code)
     value, elapsed, passes = main_res["value"], main_res["elapsed"], main_res["passes"]
     t_lloyd, t_assign = main_res["t_lloyd"], main_res["t_assign"]
     lloyd_gbs, assign_gbs, tune = main_res["lloyd_gbs"], main_res["assign_gbs"], main_res["tune"]
-    C_before, r_first_timed = main_res["C_before"], main_res["r_first_timed"]
 
     # HBM traffic per launch from the committed counter measurement, scaled
     # to this launch's units of work (null if the kernels changed since)
     traffic = None
-    rec = measured_traffic(f"lloyd_resident_metric_traffic_{args.precision}.json")
-    if rec is not None and args.workload == "metric":
+    rec = measured_traffic(f"lloyd_resident_{args.workload}_traffic_{args.precision}.json")
+    if rec is not None:
         units = float(passes.mean()) * s
         traffic = {"bytes_per_launch": rec["bytes_per_unit"] * units,
                    "read_bytes_per_unit": rec["read_bytes_per_unit"],
                    "write_bytes_per_unit": rec["write_bytes_per_unit"],
                    "algorithmic_bytes_per_unit": 4 * d, "source": rec["file"]}
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(X, C_before, r_first_timed, args, m, d, W, s, k)
-    tts = None
-    if args.tts:
-        f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
-        tts = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
 
     D = 1 << max(3, (d - 1).bit_length())  # padded width of the kernel instantiation
     roofline = {"bound": "hbm", "achieved": lloyd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -168,7 +217,7 @@ def main():
         spi = float(passes.mean()) * s
         tflops = 2.0 * k * d * spi / t_lloyd / 1e12
         roofline = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
-                    "frac": tflops / peak, "traffic": None,
+                    "frac": tflops / peak, "traffic": traffic,
                     "kernel": f"k_lloyd_resident<{D},512,{prec}>", "launch": tune,
                     "flops_per_unit": 2 * k * d, "unit_of_work": "sample-point-iter",
                     "avg_launch_ms": t_lloyd * 1e3, "hbm_gbs": lloyd_gbs,
@@ -190,15 +239,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("gmm25 m=1e7 d=32 k=25 s=1e4 workers=1024 competitive round"
                                 if args.workload == "metric" else
-                                "gmm100 rotated m=1e8 d=64 k=100 s=5e4 workers=128 competitive round"),
+                                f"gmm100 rotated m={m:.0e} d=64 k=100 s=5e4 workers=128 "
+                                f"competitive round"),
                    "m": m, "d": d, "k": k, "s": s, "workers": W, "strategy": "competitive",
                    "passes_per_step": float(passes.mean())},
         "roofline": roofline,
         "assign_sse": assign,
         "hbm_copy": copy,
-        "cpu_baseline": cpu,
-        "time_to_sse": tts,
+        "cold_round": main_res["cold"],
+        "cold_sample": cold_sample_latency(api, X, s, k, prec, args.seed),
     }
+    if main_res["check"] is not None:
+        out["error_vs_oracle"] = error_report(api, X, main_res["check"], args, m, d, s, k, prec)
     if others:
         out["other_screenings"] = {
             name: {"dtype": SCREENINGS[name][1],
@@ -214,7 +266,7 @@ def main():
                                         "decisions in FP64, so pass counts and results agree")
         out["results_identical_across_screenings"] = all(
             v["same_passes"] and v["same_sse"] for v in out["other_screenings"].values())
-    print(json.dumps(out), flush=True)
+    return out, main_res
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=5):
@@ -278,9 +330,9 @@ def run_metric(api, X, args, prec):
               file=sys.stderr, flush=True)
         del Ct
 
-    ev = {name: [] for name in ("lloyd", "assign")}
+    ev = {name: [] for name in ("lloyd", "assign", "cold")}
 
-    def step(timed):
+    def step(timed, cold=False, lab_out=None):
         plan.draw(m, idx)
         C.copy_(C_inc)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -288,7 +340,7 @@ def run_metric(api, X, args, prec):
         e2 = torch.cuda.Event(enable_timing=True)
         e3 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        plan.lloyd(X, idx, C, f_out=f, iters_out=it)
+        plan.lloyd(X, idx, C, f_out=f, iters_out=it, labels_out=lab_out)
         e1.record(stream)
         api.keep_best(C, f, C_inc, f_inc, k, d)
         plan.advance(W)
@@ -299,12 +351,30 @@ def run_metric(api, X, args, prec):
         if timed:
             ev["lloyd"].append((e0, e1))
             ev["assign"].append((e2, e3))
+        if cold:
+            ev["cold"].append((e0, e1))
         return it.clone()
 
-    for _ in range(args.warmup):
-        step(False)
+    # the first round starts from no incumbent: K-means++ seeding of every
+    # worker's sample, then passes to the stop rule (the cold round)
+    cold_passes = None
+    for w_i in range(args.warmup):
+        its_w = step(False, cold=w_i == 0)
+        if w_i == 0:
+            cold_passes = its_w
     torch.cuda.synchronize()
-    print(f"[bench] {args.warmup} warmup step(s) done", file=sys.stderr, flush=True)
+    cold = None
+    if ev["cold"]:
+        a0, a1 = ev["cold"][0]
+        cms = a0.elapsed_time(a1)
+        cp = int(cold_passes.sum().item())
+        cold = {"ms": cms, "passes": cp, "value": cp * s / (cms / 1e3),
+                "unit": "sample-point-iters/s",
+                "what": f"first round: K-means++ seeding of all {W} samples, then passes to "
+                        "the stop rule (seeding kernel + Lloyd kernel, HIP events)"}
+    print(f"[bench] {args.warmup} warmup step(s) done"
+          + (f"; cold round {cold['ms']:.2f} ms, {cold['passes']} passes" if cold else ""),
+          file=sys.stderr, flush=True)
     its = []
     C_before = C_inc.clone()
     r_first_timed = args.warmup
@@ -325,10 +395,162 @@ def run_metric(api, X, args, prec):
           f"{passes.tolist()}; lloyd {t_lloyd * 1e3:.2f} ms ({lloyd_gbs:.0f} GB/s algorithmic), "
           f"assign {t_assign * 1e3:.3f} ms ({assign_gbs:.0f} GB/s), SSE {sse.item():.6e}",
           file=sys.stderr, flush=True)
+    # one more round after the timed ones, untimed, with sample labels: its
+    # inputs and outputs feed the error report against the oracle
+    check = None
+    if getattr(args, "error_workers", None):
+        r_check = r_first_timed + args.steps
+        C_start = C_inc.clone()
+        lab_s = torch.empty(W * s, dtype=torch.int32, device=dev)
+        step(False, lab_out=lab_s)
+        torch.cuda.synchronize()
+        ws = list(args.error_workers)
+        check = {"round": r_check, "workers": ws,
+                 "C_start": C_start[ws].double().cpu().numpy(),
+                 "C": C[ws].double().cpu().numpy(), "f": f[ws].cpu().numpy(),
+                 "iters": it[ws].cpu().numpy(),
+                 "labels": lab_s.view(W, s)[ws].cpu().numpy(),
+                 "idx": idx.view(W, s)[ws].cpu().numpy(),
+                 "C_best": api.select_best(C_inc, f_inc, k, d)[0].clone(),
+                 "labels_full": labels}
     plan.close()
     return dict(value=spi / elapsed, elapsed=elapsed, passes=passes, t_lloyd=t_lloyd,
                 t_assign=t_assign, lloyd_gbs=lloyd_gbs, assign_gbs=assign_gbs, tune=tune,
-                C_before=C_before, r_first_timed=r_first_timed, sse=sse.item())
+                C_before=C_before, r_first_timed=r_first_timed, sse=sse.item(), cold=cold,
+                check=check)
+
+
+def error_report(api, X, chk, args, m, d, s, k, prec, n_rows=100_000, sse_rows=1_000_000):
+    """The GPU results of one untimed round against the FP64 oracle: the
+    Lloyd runs of the sampled workers (from the same incumbents, on the same
+    rows and random streams) and the full assignment of the round's best
+    incumbent on sampled rows of X."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    import oracle
+
+    W = args.workers
+    ws = chk["workers"]
+    t0 = time.perf_counter()
+
+    def one(q):
+        w = ws[q]
+        sid = chk["round"] * W + w
+        ii = chk["idx"][q]
+        same_draw = bool(np.array_equal(ii, oracle.draw_sample(m, s, args.seed, sid)))
+        S = X[torch.from_numpy(ii).to(X.device)].cpu().numpy()
+        ro = oracle.lloyd(S, np.arange(s), k, chk["C_start"][q].reshape(k, d), seed=args.seed,
+                          sample_id=sid, want_margins=True)
+        Cg = chk["C"][q].reshape(k, d)
+        sigma = np.sqrt(((S - S.mean(axis=0)) ** 2).sum(axis=1).mean())
+        cerr = float(np.max(np.linalg.norm(Cg - ro.C, axis=1)
+                            / (np.linalg.norm(ro.C, axis=1) + sigma)))
+        diff = chk["labels"][q] != ro.labels
+        tie = ro.margins < 1e-5
+        return {"worker": w, "sample_id": sid, "same_draw": same_draw,
+                "passes": int(chk["iters"][q]), "oracle_passes": int(ro.iters),
+                "f_rel_err": abs(float(chk["f"][q]) - ro.f) / ro.f,
+                "centroid_err": cerr,
+                "label_mismatches": int((diff & ~tie).sum()),
+                "label_mismatches_near_ties": int((diff & tie).sum()),
+                "oracle_clean": bool(ro.diag["min_label_margin"] >= 1e-10
+                                     and ro.diag["min_draw_margin"] >= 1e-10
+                                     and ro.diag["min_cand_margin"] >= 1e-10
+                                     and ro.diag["min_stop_margin"] >= 1e-10)}
+
+    with cf.ThreadPoolExecutor(max_workers=len(ws)) as ex:
+        per = list(ex.map(one, range(len(ws))))
+    rng = np.random.default_rng(12345)
+    rows = torch.from_numpy(np.sort(rng.choice(m, n_rows, replace=False))).to(X.device)
+    Cb = chk["C_best"].view(k, d)
+    o = oracle.assign_sse(X[rows].cpu().numpy(), Cb.double().cpu().numpy(), want_margins=True)
+    lab = chk["labels_full"][rows].cpu().numpy()
+    diff = lab != o["labels"]
+    tie = o["margins"] < 1e-5
+    rows2 = torch.from_numpy(np.sort(rng.choice(m, min(m, sse_rows), replace=False))).to(X.device)
+    Xs2 = X[rows2].contiguous()
+    _, _, sse_g = api.assign_sse(Xs2, Cb.contiguous(), want_labels=False, want_counts=False,
+                                 precision=prec)
+    o2 = oracle.assign_sse(Xs2.cpu().numpy(), Cb.double().cpu().numpy(), want_labels=False)
+    return {
+        "subset": (f"round {chk['round']} (untimed, after the timed steps), workers {ws}: "
+                   f"Lloyd from the same incumbents on the same rows and streams; full "
+                   f"assignment of that round's best incumbent: labels of {n_rows} random rows, "
+                   f"objective over {min(m, sse_rows)} random rows"),
+        "lloyd": per,
+        "assign_labels": {"rows": n_rows, "mismatches": int((diff & ~tie).sum()),
+                          "mismatches_near_ties": int((diff & tie).sum()),
+                          "near_ties": int(tie.sum())},
+        "assign_sse_rows": {"rows": min(m, sse_rows), "gpu": sse_g.item(), "oracle": o2["sse"],
+                            "rel_err": abs(sse_g.item() - o2["sse"]) / o2["sse"]},
+        "seconds": time.perf_counter() - t0,
+    }
+
+
+def cold_sample_latency(api, X, s, k, prec, seed, reps=10):
+    """One cold sample on its own (the plain per-sample form's first
+    sample): K-means++ seeding and passes to the stop rule in one
+    hpc_lloyd_batch call, and the seeding alone (hpc_seed_kmeanspp); median
+    of `reps` HIP-event timings, each on a new sample."""
+    import numpy as np
+    import torch
+
+    m, d = X.shape
+    idx = torch.empty(s, dtype=torch.int64, device=X.device)
+    out = {}
+    for what in ("lloyd", "seed"):
+        ts, passes = [], []
+        for r in range(reps + 2):
+            api.draw_sample(m, s, seed, 10_000_000 + r, out=idx)
+            C = torch.full((k, d), float("nan"), device=X.device)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            if what == "lloyd":
+                desc, _, _ = api.make_desc([s], [k], seed=seed, sample_id=[10_000_000 + r], d=d)
+                e0.record()
+                _, it, _ = api.lloyd_batch(X, idx, desc, C, precision=prec)
+                e1.record()
+            else:
+                e0.record()
+                api.seed_kmeanspp(X, idx, k, seed=seed, sample_id=10_000_000 + r, C=C,
+                                  want_chosen=False)
+                e1.record()
+            torch.cuda.synchronize()
+            if r >= 2:
+                ts.append(e0.elapsed_time(e1))
+                if what == "lloyd":
+                    passes.append(int(it.item()))
+        out[what] = {"ms_median": float(np.median(ts)), "ms_min": float(np.min(ts)),
+                     "ms_max": float(np.max(ts))}
+        if passes:
+            out[what]["passes_mean"] = float(np.mean(passes))
+    out["what"] = (f"one cold sample (s={s}, k={k}, d={d}), {reps} samples: seeding + passes "
+                   "(hpc_lloyd_batch) and seeding alone (hpc_seed_kmeanspp), HIP events")
+    return out
+
+
+def host_cpu():
+    """The host's CPU model, logical CPU count and this process's CPU share."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(share, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else share
+    return {"model": model, "logical_cpus": os.cpu_count(), "affinity_cpus": share,
+            "omp_num_threads": omp, "threads_all": max(1, threads)}
 
 
 def pmc_target(api, X, m, d, W, s, k, prec, seed):
@@ -382,16 +604,23 @@ def measured_traffic(kernel_file):
     return rec
 
 
-def _first_reach(api, X, hist, times, target, precision):
-    """Index and time of the first recorded incumbent whose full-data SSE is
-    within the target (SSE evaluated after the run, not timed)."""
-    for i in range(len(times)):
+def _sses(api, X, hist, precision):
+    """Full-data SSE of every recorded incumbent (evaluated after the run,
+    not timed)."""
+    out = []
+    for i in range(hist.shape[0]):
         _, _, sse = api.assign_sse(X, hist[i], want_labels=False, want_counts=False,
                                    precision=precision)
-        v = sse.item()
+        out.append(sse.item())
+    return out
+
+
+def _first_reach(sses, times, target):
+    """Index, time and SSE of the first recorded incumbent within target."""
+    for i, v in enumerate(sses):
         if v <= target:
             return i, times[i], v
-    return None, None, v
+    return None, None, sses[-1] if sses else None
 
 
 def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
@@ -440,9 +669,18 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
         res["f_ref_source"] = "oracle"
     res["f_ref"] = f_ref
     target = f_ref * (1 + 1e-3)
-    i, t, v = _first_reach(api, X, hist, t_plain, target, api.PREC_FP32)
+    # a second, tighter threshold: the quality of the oracle's 64-sample run
+    # itself (within the SSE tolerance), which the plain form reaches only
+    # after its best sample and a batched round may reach at once
+    target2 = f_ref * (1 + 1e-6)
+    res["threshold2_rel"] = 1e-6
+    sses = _sses(api, X, hist, api.PREC_FP32)
+    i, t, v = _first_reach(sses, t_plain, target)
+    i2, t2, _ = _first_reach(sses, t_plain, target2)
     res["plain_fp32_per_sample"] = {"ms": t, "samples": None if i is None else i + 1,
-                                    "sse": v, "ms_all": t_plain[-1]}
+                                    "sse": v, "ms_all": t_plain[-1],
+                                    "ms_threshold2": t2,
+                                    "samples_threshold2": None if i2 is None else i2 + 1}
 
     model = None
     if args.train_pairs > 0:
@@ -498,8 +736,11 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
             evs[r + 1].record(stream)
         torch.cuda.synchronize()
         times = [evs[0].elapsed_time(e) for e in evs[1:]]
-        i, t, v = _first_reach(api, X, hist, times, target, prec)
+        sses = _sses(api, X, hist, prec)
+        i, t, v = _first_reach(sses, times, target)
+        i2, t2, _ = _first_reach(sses, times, target2)
         res[name] = {"ms": t, "rounds": None if i is None else i + 1, "sse": v,
+                     "ms_threshold2": t2, "rounds_threshold2": None if i2 is None else i2 + 1,
                      "ms_per_round": [round(x, 3) for x in np.diff([0.0] + times)]}
         if acc is not None:
             res[name]["accepted_frac"] = acc.float().mean().item()
@@ -507,46 +748,59 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
     best = res.get("batched_bf16_learned") or res["batched_bf16"]
     p = res["plain_fp32_per_sample"]["ms"]
     res["speedup_vs_plain"] = (p / best["ms"]) if (p and best["ms"]) else None
+    p2 = res["plain_fp32_per_sample"]["ms_threshold2"]
+    res["speedup_vs_plain_threshold2"] = ((p2 / best["ms_threshold2"])
+                                          if (p2 and best["ms_threshold2"]) else None)
     if model is not None:
         model.close()
     return res
 
 
 def cpu_baseline(X, C_start, r, args, m, d, W, s, k):
-    """The FP64 oracle on a bounded sample of the same workload: samples of
+    """The FP64 oracle on bounded samples of the same workload: samples of
     the first timed round and the rounds after it, from the incumbents the
-    timed round started from, on the host's cores (samples run side by
-    side), for about args.cpu_seconds of CPU work."""
+    timed round started from, once on one thread and once on every thread
+    of the host share (samples run side by side), each for about half of
+    args.cpu_seconds of CPU time."""
     import numpy as np
 
     import oracle
-    from paper_2311_04517_amd import api
 
-    n_threads = max(1, min(16, os.cpu_count() or 1))
+    cpu = host_cpu()
     Xn = X.cpu().numpy()
     C_host = C_start.double().cpu().numpy()
-    done_spi, done_t, done_n = 0, 0.0, 0
-    per = n_threads
-    # the timed round's samples, then the next rounds' (each from its
-    # worker's incumbent at the start of the timed round), in groups of
-    # n_threads samples until the time budget is spent
-    while done_t < args.cpu_seconds and done_n < 64 * W:
-        ids = [r * W + w for w in range(done_n, done_n + per)]
-        idx = np.concatenate([oracle.draw_sample(m, s, args.seed, i) for i in ids])
-        Cb = np.concatenate([C_host[i % W].ravel() for i in range(done_n, done_n + per)])
-        desc = dict(idx_offset=np.arange(per) * s, s=[s] * per, k=[k] * per,
-                    c_offset=np.arange(per) * k * d, seed=[args.seed] * per, sample_id=ids)
-        t0 = time.perf_counter()
-        o = oracle.lloyd_batch(Xn, idx, desc, Cb, n_threads=n_threads)
-        done_t += time.perf_counter() - t0
-        done_spi += int(o["iters"].sum()) * s
-        done_n += per
-    del api
-    out = {"value": done_spi / done_t, "unit": "sample-point-iters/s", "cores": n_threads,
-           "kind": "oracle",
-           "sample": f"{done_n} samples of the workload (the timed round's first, then the next "
-                     f"rounds', each from its worker's incumbent at the start of the timed "
-                     f"round), {done_t:.1f}s of CPU work on {n_threads} threads"}
+
+    def rate(n_threads, budget, start):
+        done_spi, done_t, done_n = 0, 0.0, 0
+        per = n_threads
+        # the timed round's samples, then the next rounds' (each from its
+        # worker's incumbent at the start of the timed round), in groups of
+        # n_threads samples until the time budget is spent
+        while done_t < budget and done_n < 64 * W:
+            ids = [r * W + w for w in range(start + done_n, start + done_n + per)]
+            idx = np.concatenate([oracle.draw_sample(m, s, args.seed, i) for i in ids])
+            Cb = np.concatenate([C_host[i % W].ravel()
+                                 for i in range(start + done_n, start + done_n + per)])
+            desc = dict(idx_offset=np.arange(per) * s, s=[s] * per, k=[k] * per,
+                        c_offset=np.arange(per) * k * d, seed=[args.seed] * per, sample_id=ids)
+            t0 = time.perf_counter()
+            o = oracle.lloyd_batch(Xn, idx, desc, Cb, n_threads=n_threads)
+            done_t += time.perf_counter() - t0
+            done_spi += int(o["iters"].sum()) * s
+            done_n += per
+        return done_spi / done_t, done_t, done_n
+
+    n_all = cpu["threads_all"]
+    v1, t1, n1 = rate(1, args.cpu_seconds / 2, 0)
+    va, ta, na = rate(n_all, args.cpu_seconds / 2, 0)
+    out = {"value": va, "unit": "sample-point-iters/s", "cores": n_all, "kind": "oracle",
+           "sample": (f"samples of the workload (the timed round's first, then the next "
+                      f"rounds', each from its worker's incumbent at the start of the timed "
+                      f"round): {na} samples in {ta:.1f}s of wall time on {n_all} threads; "
+                      f"single thread: {n1} samples in {t1:.1f}s"),
+           "single_core": {"value": v1, "cores": 1, "samples": n1, "seconds": t1},
+           "all_cores": {"value": va, "cores": n_all, "samples": na, "seconds": ta},
+           "cpu": cpu}
     if args.tts:
         # the time-to-SSE threshold: the single-worker method (one worker,
         # keep-the-best over N samples, then the full assignment), FP64

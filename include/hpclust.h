@@ -277,7 +277,11 @@ typedef struct {
                           (one per wave removes LDS atomic contention
                           between waves); 0 = as many as fit in 64 KiB     */
     int32_t order;     /* 0: longest sample first; 1: descriptor order      */
-    int32_t reserved;  /* must be 0                                         */
+    int32_t seed_team; /* workgroups per cold sample in the K-means++ seeding
+                          kernel, 0..64; 0 = chosen from the free capacity  */
+    int32_t seed_inflight; /* cold samples seeded at once at most (0 = as many
+                          teams as are resident; fewer keep the samples'
+                          rows and weights in the last-level cache)        */
 } hpc_tune;
 
 /* Create a plan on the current device for n_samples samples (desc: HOST
@@ -296,7 +300,8 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc *desc, int32_t n_samples, i
 int hpc_plan_destroy(hpc_plan plan);
 
 /* Set / read the launch configuration.  Errors: wg_per_cu < 0, copies
- * outside [0, 4], order outside {0, 1}, reserved != 0, or a configuration
+ * outside [0, 4], order outside {0, 1}, seed_team outside [0, 64], seed_inflight < 0,
+ * or a configuration
  * whose LDS does not fit.  A captured round keeps the configuration it was
  * captured with. */
 int hpc_plan_set_tune(hpc_plan plan, const hpc_tune *tune);

@@ -44,11 +44,13 @@ class Tune(ct.Structure):
         ("wg_per_cu", ct.c_int32),
         ("copies", ct.c_int32),
         ("order", ct.c_int32),
-        ("reserved", ct.c_int32),
+        ("seed_team", ct.c_int32),
+        ("seed_inflight", ct.c_int32),
     ]
 
     def as_dict(self):
-        return {"wg_per_cu": self.wg_per_cu, "copies": self.copies, "order": self.order}
+        return {"wg_per_cu": self.wg_per_cu, "copies": self.copies, "order": self.order,
+                "seed_team": self.seed_team, "seed_inflight": self.seed_inflight}
 
 
 class HpcError(RuntimeError):

@@ -208,8 +208,8 @@ class Plan:
         check(lib().hpc_plan_get_tune(self._h, ct.byref(t)), "hpc_plan_get_tune")
         return t
 
-    def set_tune(self, wg_per_cu=0, copies=0, order=0):
-        t = Tune(wg_per_cu, copies, order, 0)
+    def set_tune(self, wg_per_cu=0, copies=0, order=0, seed_team=0, seed_inflight=0):
+        t = Tune(wg_per_cu, copies, order, seed_team, seed_inflight)
         check(lib().hpc_plan_set_tune(self._h, ct.byref(t)), "hpc_plan_set_tune")
 
     def tune_key(self) -> str:

@@ -20,6 +20,7 @@
 #include "assign_misc.hpp"
 #include "common.hpp"
 #include "host_util.hpp"
+#include "kmeanspp_team.hpp"
 #include "lloyd_resident.hpp"
 
 namespace {
@@ -295,6 +296,129 @@ int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, const ResGeo& g,
     });
 }
 
+// --------------------------------------------------------------------------
+// K-means++ seeding of cold samples by teams of workgroups.
+// --------------------------------------------------------------------------
+constexpr int kKppNT = 256;        // threads per workgroup of the seeding kernel
+constexpr int kKppMinSlice = 512;  // a team grows only while slices keep this many points
+constexpr int kKppMaxTeam = hpc::kMaxTeam;
+constexpr int kKppMaxWgPerCu = 8;  // bound on resident seeding workgroups per CU (buffers)
+
+struct KppGeo {
+    int team = 1;     // workgroups per sample
+    int n_teams = 0;  // 0: no launch (the Lloyd kernel seeds every sample itself)
+    int grid = 0;
+    int ngmax = 0;
+    size_t lds = 0;
+};
+
+// Launch shape of the seeding kernel for n samples (largest s smax, largest
+// k kmax).  team_req 0 picks the team size from the free capacity: as many
+// workgroups per sample as the resident grid allows for all samples at once,
+// at most one per kKppMinSlice points.  inflight_req caps the teams working
+// at once (0: as many as are resident; fewer keep the samples' rows and
+// weights within the last-level cache).  The grid is always resident at
+// once, which the teams' exchanges rely on (they wait on each other); a team
+// takes its samples in turn from the processing order.
+template <int D>
+int kpp_geometry(int n, int smax, int kmax, int team_req, int inflight_req, KppGeo* g) {
+    *g = KppGeo{};
+    int lds_max = 0, cus = 0;
+    int rc = max_dyn_lds(&lds_max);
+    if (rc) return rc;
+    rc = device_cus(&cus);
+    if (rc) return rc;
+    auto kern = hpc::k_kmeanspp_team<D, kKppNT>;
+    auto shape = [&](int T, int* ngmax, size_t* lds, int64_t* cap) -> int {
+        const int64_t per = ((smax + (int64_t)T - 1) / T + hpc::kKppGroup - 1) / hpc::kKppGroup;
+        *ngmax = (int)std::max<int64_t>(1, per);
+        *lds = hpc::kpp_lds_bytes<D, kKppNT>(*ngmax, kmax);
+        *cap = 0;
+        if (*lds > (size_t)lds_max) return HPC_OK;
+        if (*lds > 64 * 1024)
+            HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)*lds));
+        int per_cu = 0;
+        HPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kKppNT, *lds));
+        *cap = (int64_t)cus * std::min(std::max(per_cu, 0), kKppMaxWgPerCu);
+        return HPC_OK;
+    };
+    int ngmax = 0;
+    size_t lds = 0;
+    int64_t cap = 0;
+    rc = shape(1, &ngmax, &lds, &cap);
+    if (rc) return rc;
+    int T = 1;
+    if (team_req > 0) {
+        T = std::min(team_req, kKppMaxTeam);
+    } else if (cap > 0) {
+        const int64_t by_cap = cap / n;
+        const int64_t by_size = std::max<int64_t>(1, smax / kKppMinSlice);
+        T = (int)std::max<int64_t>(1, std::min<int64_t>({by_cap, by_size, (int64_t)kKppMaxTeam}));
+    }
+    if (T > 1) {
+        rc = shape(T, &ngmax, &lds, &cap);
+        if (rc) return rc;
+        if (cap < T) {  // not even one team resident
+            T = 1;
+            rc = shape(1, &ngmax, &lds, &cap);
+            if (rc) return rc;
+        }
+    }
+    if (cap == 0) return HPC_OK;  // the slices do not fit in LDS: seeded in the Lloyd kernel
+    int64_t teams = cap / T;
+    if (inflight_req > 0) teams = std::min<int64_t>(teams, inflight_req);
+    g->team = T;
+    g->n_teams = (int)std::min<int64_t>(n, teams);
+    g->grid = g->n_teams * T;
+    g->ngmax = ngmax;
+    g->lds = lds;
+    return HPC_OK;
+}
+
+int kpp_geo(int D, int n, int smax, int kmax, int team_req, int inflight_req, KppGeo* g) {
+    switch (D) {
+        case 8: return kpp_geometry<8>(n, smax, kmax, team_req, inflight_req, g);
+        case 16: return kpp_geometry<16>(n, smax, kmax, team_req, inflight_req, g);
+        case 32: return kpp_geometry<32>(n, smax, kmax, team_req, inflight_req, g);
+        case 64: return kpp_geometry<64>(n, smax, kmax, team_req, inflight_req, g);
+        case 128: return kpp_geometry<128>(n, smax, kmax, team_req, inflight_req, g);
+    }
+    return fail(HPC_ERR_UNSUPPORTED, "seeding: padded dimension %d", D);
+}
+
+// Bytes of the seeding kernel's team flags and exchange slots for at most
+// `grid` workgroups (one team per workgroup at most).
+size_t kpp_flag_bytes(int64_t grid) { return (size_t)grid * 16; }
+size_t kpp_slot_bytes(int64_t grid) { return (size_t)grid * 2 * hpc::kTeamSlot * 8; }
+
+// Enqueue the flag resets and the seeding kernel (kernel launches only).
+int launch_kpp(int D, hpc::KppArgs a, const KppGeo& g, hipStream_t st) {
+    if (g.grid == 0) return HPC_OK;
+    a.team = g.team;
+    a.n_teams = g.n_teams;
+    a.ngmax = g.ngmax;
+    hipLaunchKernelGGL(hpc::k_fill_i32, dim3(1), dim3(64), 0, st, a.queue, (int64_t)1, 0);
+    hipLaunchKernelGGL(hpc::k_fill_i32, dim3((4 * g.n_teams + 255) / 256), dim3(256), 0, st,
+                       a.tflag, (int64_t)4 * g.n_teams, 0);
+#define HPC_KPP(DD)                                                                           \
+    case DD:                                                                                  \
+        hipLaunchKernelGGL((hpc::k_kmeanspp_team<DD, kKppNT>), dim3(g.grid), dim3(kKppNT), g.lds, \
+                           st, a);                                                            \
+        break
+    switch (D) {
+        HPC_KPP(8);
+        HPC_KPP(16);
+        HPC_KPP(32);
+        HPC_KPP(64);
+        HPC_KPP(128);
+        default: return fail(HPC_ERR_UNSUPPORTED, "seeding: padded dimension %d", D);
+    }
+#undef HPC_KPP
+    HPC_HIP(hipGetLastError());
+    return HPC_OK;
+}
+
 // Resident waves per CU of k_assign_sse<D, NT, PREC> with `lds` bytes of
 // LDS per workgroup (0 if it does not fit); sets the attribute allowing
 // more than 64 KiB.
@@ -435,6 +559,32 @@ std::vector<int32_t> longest_first(const hpc_sample_desc* desc, int32_t n) {
     return order;
 }
 
+// Arguments of the seeding kernel for the batch of a resident launch.
+hpc::KppArgs kpp_args(const hpc::LloydArgs& a, uint32_t tag, uint32_t call_id, int n_cand,
+                      int32_t* queue, int32_t* tflag, double* tx) {
+    hpc::KppArgs k{};
+    k.X = a.X;
+    k.m = a.m;
+    k.d = a.d;
+    k.idx = a.idx;
+    k.desc = a.desc;
+    k.order = a.order;
+    k.n_samples = a.n_samples;
+    k.C = a.C;
+    k.n_cand = n_cand;
+    k.tag = tag;
+    k.call_id = call_id;
+    k.chosen = a.chosen;
+    k.vec4 = a.vec4;
+    k.sbuf = a.sbuf;
+    k.d2buf = a.d2buf;
+    k.kmax = a.kmax;
+    k.queue = queue;
+    k.tflag = tflag;
+    k.tx = tx;
+    return k;
+}
+
 // Run the resident kernel over a batch (Lloyd, or seeding only).
 int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64_t idx_len,
                  const hpc_sample_desc* desc, int32_t n, float* C, int32_t max_iter,
@@ -454,8 +604,14 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     const size_t sbuf_b = (size_t)idx_len * D * 4;
     const size_t xbuf_b = g.split == 2 ? xbuf_doubles(n, kmax, D) * 8 : 0;
     const size_t xflag_b = g.split == 2 ? (size_t)n * 16 : 0;
+    int smax = 0;
+    for (int32_t b = 0; b < n; ++b) smax = std::max(smax, desc[b].s);
+    KppGeo kg;
+    rc = kpp_geo(D, n, smax, kmax, 0, 0, &kg);
+    if (rc) return rc;
+    const size_t kflag_b = kpp_flag_bytes(kg.grid), kslot_b = kpp_slot_bytes(kg.grid);
     const size_t need = Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 40,
-                                     (size_t)idx_len * 4, xbuf_b, xflag_b});
+                                     (size_t)idx_len * 4, xbuf_b, xflag_b, kflag_b, kslot_b});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
@@ -466,6 +622,8 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     int32_t* lbuf = static_cast<int32_t*>(cv.take((size_t)idx_len * 4));
     double* xbuf = static_cast<double*>(cv.take(xbuf_b));
     int32_t* xflag = static_cast<int32_t*>(cv.take(xflag_b));
+    int32_t* kflag = static_cast<int32_t*>(cv.take(kflag_b));
+    double* kslot = static_cast<double*>(cv.take(kslot_b));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
     memcpy(host.data() + desc_b, order.data(), order_b);
@@ -497,6 +655,16 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     a.vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
     a.xbuf = g.split == 2 ? xbuf : nullptr;
     a.xflag = g.split == 2 ? xflag : nullptr;
+    // cold samples are seeded first by the team kernel (stream tag SEED and
+    // the caller's call_id for the seeding call; RESEED and 0, the stream of
+    // a Lloyd cold start, otherwise); the resident kernel then seeds only
+    // what is left: partially valid blocks, or samples of a team that gave up
+    if (seed_only && chosen)
+        hipLaunchKernelGGL(hpc::k_fill_i32, dim3(1), dim3(256), 0, st, chosen, (int64_t)kmax, -1);
+    const hpc::KppArgs ka = kpp_args(a, seed_only ? hpc::kTagSeed : hpc::kTagReseed,
+                                     seed_only ? call_id : 0u, n_cand, queue + 16, kflag, kslot);
+    rc = launch_kpp(D, ka, kg, st);
+    if (rc) return rc;
     return dispatch_resident(D, precision, a, g, st);
 }
 
@@ -528,8 +696,13 @@ struct hpc_plan_s {
     float* tC = nullptr;  // autotuner scratch
     double* tf = nullptr;
     int32_t* tit = nullptr;
+    int32_t* kflag = nullptr;  // seeding teams' flags and exchange slots
+    double* kslot = nullptr;
+    int64_t kgrid_max = 0;     // workgroups those buffers serve
+    int smax = 0;
     hpc_tune tune{};
     ResGeo geo;
+    KppGeo kgeo;
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -586,10 +759,26 @@ hpc::LloydArgs plan_args(hpc_plan p, const float* X, int64_t m, const int64_t* i
     return a;
 }
 
+// Seeding of the cold samples (team kernel), then the resident Lloyd kernel.
 int plan_launch(hpc_plan p, const hpc::LloydArgs& a, const ResGeo& g, hipStream_t st) {
+    const hpc::KppArgs ka =
+        kpp_args(a, hpc::kTagReseed, 0u, 3, p->queue + 16, p->kflag, p->kslot);
+    int rc = launch_kpp(p->D, ka, p->kgeo, st);
+    if (rc) return rc;
     return with_dp(p->D, p->prec, [&](auto Dc, auto Pc) {
         return launch_resident<decltype(Dc)::value, decltype(Pc)::value>(a, g, st);
     });
+}
+
+// The seeding kernel's launch shape for a plan and a team request (the
+// buffers allocated with the plan bound the grid).
+int plan_kpp_geometry(hpc_plan p, int team_req, int inflight_req, KppGeo* g) {
+    int rc = kpp_geo(p->D, p->n, p->smax, p->kmax, team_req, inflight_req, g);
+    if (rc) return rc;
+    if (g->grid > p->kgrid_max)
+        return fail(HPC_ERR_UNSUPPORTED, "seeding grid of %d workgroups exceeds the plan's %lld",
+                    g->grid, (long long)p->kgrid_max);
+    return HPC_OK;
 }
 
 int lloyd_opts_ok(const char* where, const float* X, int64_t m, const void* idx, const void* C,
@@ -924,9 +1113,15 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     const size_t d2_b = (size_t)idx_len * 40;  // D^2 and up to four candidate distances
     const size_t xbuf_b = shareable ? xbuf_doubles(n_samples, kmax, p->D) * 8 : 0;
     const size_t xflag_b = shareable ? (size_t)n_samples * 16 : 0;
+    for (int32_t b = 0; b < n_samples; ++b) p->smax = std::max(p->smax, desc[b].s);
+    int cus = 0;
+    rc = device_cus(&cus);
+    if (rc) return cleanup(rc);
+    p->kgrid_max = (int64_t)cus * kKppMaxWgPerCu;
+    const size_t kflag_b = kpp_flag_bytes(p->kgrid_max), kslot_b = kpp_slot_bytes(p->kgrid_max);
     const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)idx_len * 4,
                                      (size_t)c_len * 4, (size_t)n_samples * 8,
-                                     (size_t)n_samples * 4, xbuf_b, xflag_b});
+                                     (size_t)n_samples * 4, xbuf_b, xflag_b, kflag_b, kslot_b});
     hipError_t e = hipMalloc(&p->mem, need);
     if (e != hipSuccess) {
         p->mem = nullptr;
@@ -947,7 +1142,12 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     if (shareable) {
         p->xbuf = static_cast<double*>(cv.take(xbuf_b));
         p->xflag = static_cast<int32_t*>(cv.take(xflag_b));
+    } else {
+        (void)cv.take(xbuf_b);
+        (void)cv.take(xflag_b);
     }
+    p->kflag = static_cast<int32_t*>(cv.take(kflag_b));
+    p->kslot = static_cast<double*>(cv.take(kslot_b));
     std::vector<int32_t> orders = longest_first(desc, n_samples);
     orders.resize((size_t)2 * n_samples);
     std::iota(orders.begin() + n_samples, orders.end(), 0);
@@ -956,6 +1156,8 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
         hipMemcpy(p->order_dev, orders.data(), order_b, hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(HPC_ERR_HIP, "hpc_plan_create: descriptor upload failed"));
     rc = plan_geometry(p, p->tune, &p->geo);
+    if (rc) return cleanup(rc);
+    rc = plan_kpp_geometry(p, p->tune.seed_team, p->tune.seed_inflight, &p->kgeo);
     if (rc) return cleanup(rc);
     *out = p;
     return HPC_OK;
@@ -979,15 +1181,21 @@ int hpc_plan_set_tune(hpc_plan plan, const hpc_tune* tune) {
     int rc = plan_check(plan, "hpc_plan_set_tune");
     if (rc) return rc;
     if (!tune || tune->wg_per_cu < 0 || tune->copies < 0 || tune->copies > 4 || tune->order < 0 ||
-        tune->order > 1 || tune->reserved != 0)
+        tune->order > 1 || tune->seed_team < 0 || tune->seed_team > kKppMaxTeam ||
+        tune->seed_inflight < 0)
         return fail(HPC_ERR_INVALID_ARG,
                     "hpc_plan_set_tune: need wg_per_cu>=0, copies in [0,4], order in {0,1}, "
-                    "reserved 0");
+                    "seed_team in [0,%d], seed_inflight>=0",
+                    kKppMaxTeam);
     ResGeo g;
     rc = plan_geometry(plan, *tune, &g);
     if (rc) return rc;
+    KppGeo kg;
+    rc = plan_kpp_geometry(plan, tune->seed_team, tune->seed_inflight, &kg);
+    if (rc) return rc;
     plan->tune = *tune;
     plan->geo = g;
+    plan->kgeo = kg;
     return HPC_OK;
 }
 
@@ -1028,7 +1236,7 @@ int hpc_plan_autotune(hpc_plan plan, const float* X, int64_t m, const int64_t* i
         ResGeo g;
         if (plan_geometry(plan, t, &g) != HPC_OK) continue;  // does not fit: skip
         for (int w = 1; w <= g.per_cu_max; ++w)
-            for (int o = 0; o <= (uneven ? 1 : 0); ++o) cand.push_back(hpc_tune{w, copies, o, 0});
+            for (int o = 0; o <= (uneven ? 1 : 0); ++o) cand.push_back(hpc_tune{w, copies, o, 0, 0});
     }
     if (cand.empty()) return fail(HPC_ERR_UNSUPPORTED, "hpc_plan_autotune: no configuration fits");
     hipEvent_t e0, e1;

@@ -1,0 +1,614 @@
+// K-means++ seeding of cold samples (Section 3: the first sample's centroids
+// come from K-means++; Section 6.5: three candidate points per new centroid)
+// by teams of workgroups.
+//
+// A cold sample (every centroid row degenerate) is split over a team of T
+// workgroups, each owning a contiguous slice of the sample's points in
+// index order.  Each of the k - 1 greedy steps then costs one pass over the
+// slice per workgroup plus two exchanges between the team's workgroups:
+//
+//   1. every workgroup knows every slice's total weight W_b = sum of D^2,
+//      so all of them compute the same D^2-weighted targets; the workgroup
+//      whose slice holds a target finds the point (inverse CDF in index
+//      order) and publishes it;                               -- exchange A
+//   2. every workgroup computes, for its slice and each candidate t, the
+//      would-be weights min(|x - c_t|^2, D^2), their sums per group of 256
+//      points and over the slice, and publishes the slice sums;  -- exchange B
+//   3. every workgroup adds the slice sums in team order, keeps the
+//      candidate of smallest potential (lowest t on ties) and adopts that
+//      candidate's weights: the slice sums are already the next W_b.
+//
+// With T = 1 there is no exchange and the workgroup runs the same steps
+// alone (batches of many cold samples).  Everything a decision depends on
+// is FP64: distances (FP32 coordinates, exact FP64 differences), weights,
+// sums, potentials, targets; the decisions are then those of an FP64
+// evaluation up to the order of the sums.
+//
+// Layout (per point, thread-per-point): a wave takes groups of 256 points
+// (four tiles of 64, one point per lane) of its workgroup's slice; a lane
+// reads its point's whole row (stride D, zero padded) from the gathered
+// copy of the sample, the next tile's row being in flight while one is
+// processed.  The candidate rows are FP64 in LDS (broadcast reads).  D^2
+// lives in five rotating buffers of s doubles per sample: the weights of
+// the step's candidates go to the four buffers not read, and the kept
+// candidate's buffer becomes the current one, so no pass updates D^2.
+// Group sums live in LDS, one array per buffer, and guide the inverse-CDF
+// search to one group of 256 weights.
+//
+// Exchanges: per team a monotonic arrival counter and per workgroup a slot
+// of eight doubles (two step parities); a workgroup publishes its slot,
+// fences it at device scope, counts its arrival and waits for the whole
+// team, within a bounded spin.  A team that runs out of the spin (not
+// expected: the host launches a team form only when every workgroup of the
+// grid is resident at once) gives up: its workgroups leave the kernel and
+// the rows of the samples it has not finished stay degenerate, which the
+// Lloyd kernel then seeds itself from the same random stream.
+#pragma once
+
+#include "common.hpp"
+
+namespace hpc {
+
+constexpr int kKppGroup = 256;            // points per group sum (four tiles of 64)
+constexpr int kKppBuffers = 5;            // rotating D^2 buffers per sample
+constexpr int kTeamSpinLimit = 1 << 20;   // about a second of waiting per exchange
+constexpr int kTeamSlot = 8;              // doubles per workgroup slot and parity
+
+struct KppArgs {
+    const float* X;
+    int64_t m;
+    int32_t d;
+    const int64_t* idx;
+    const hpc_sample_desc* desc;
+    const int32_t* order;  // processing order (longest first); may be null
+    int32_t n_samples;
+    float* C;              // centroid blocks; a sample is cold when all its rows are degenerate
+    int32_t n_cand;        // candidates per step, 1..4
+    uint32_t tag;          // stream tag (kTagSeed for the seeding call, kTagReseed in Lloyd)
+    uint32_t call_id;
+    int32_t* chosen;       // nullable: picked sample-local index per row (first sample)
+    int32_t vec4;          // rows of X are 16-byte aligned (d % 4 == 0, aligned base)
+    float* sbuf;           // gathered rows, by idx_offset, stride D
+    double* d2buf;         // kKppBuffers * s doubles per sample at kKppBuffers * idx_offset
+    int32_t team;          // workgroups per sample (T)
+    int32_t n_teams;       // grid = n_teams * team
+    int32_t ngmax;         // group sums per buffer in LDS (largest slice / 256)
+    int32_t kmax;
+    int32_t* queue;        // next task for T == 1 (zeroed per launch)
+    int32_t* tflag;        // per team: arrivals, abort (zeroed per launch)
+    double* tx;            // per team 2 * T slots of kTeamSlot doubles
+};
+
+constexpr int kMaxTeam = 64;               // workgroups per team at most
+
+template <int D, int NT>
+__host__ __device__ inline size_t kpp_lds_bytes(int ngmax, int kmax) {
+    return (size_t)kKppBuffers * ngmax * 8 + 4 * (size_t)D * 8 + 4 * (NT / kWave) * 8 +
+           (size_t)kMaxTeam * 8 + (size_t)kMaxTeam * kTeamSlot * 8 + 8 * 8 +
+           ((size_t)kmax * 4 + 15) / 16 * 16 + 64 * 4;
+}
+
+// Team barrier number e (every workgroup of the team calls it with the same
+// e, from one thread, after its slot is stored and fenced).  False if the
+// team gave up (abort flag) or the wait ran out, which then sets the flag.
+__device__ inline bool team_barrier(int32_t* flags, int T, int e) {
+    __hip_atomic_fetch_add(flags, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = T * (e + 1);
+    for (int spin = 0;; ++spin) {
+        if (__hip_atomic_load(flags, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target)
+            return true;
+        if (__hip_atomic_load(flags + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return false;
+        if (spin >= kTeamSpinLimit) {
+            __hip_atomic_store(flags + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes (lane order).
+__device__ __forceinline__ double wave_incl_scan(double v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// The inverse-CDF step of K-means++ inside one slice, by one whole wave:
+// the first point i of [lo, hi) (index order) at which carry plus the
+// running weight exceeds x.  gt: the slice's group sums (LDS), w: the
+// sample's weights.  Returns -1 if no group's running sum exceeds x, -2 if
+// a group does but, by rounding, none of its points (every lane gets the
+// same answer).
+__device__ inline int kpp_find(const double* gt, int ngroups, const double* __restrict__ w, int lo,
+                               int hi, double carry, double x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int q = -1;
+    for (int base = 0; base < ngroups; base += kWave) {
+        const int gi = base + lane;
+        const double v = gi < ngroups ? gt[gi] : 0.0;
+        const double inc = wave_incl_scan(v);
+        const double run = carry + inc;
+        const unsigned long long hit = __ballot(gi < ngroups && run > x);
+        if (hit) {
+            const int l = __ffsll((long long)hit) - 1;
+            const double ex = __shfl(inc - v, l, kWave);  // before group base + l
+            carry = carry + ex;
+            q = base + l;
+            break;
+        }
+        carry = __shfl(run, kWave - 1, kWave);
+    }
+    if (q < 0) return -1;
+    const int g0 = lo + q * kKppGroup;
+#pragma unroll
+    for (int u = 0; u < kKppGroup / kWave; ++u) {
+        const int i = g0 + u * kWave + lane;
+        const double v = i < hi ? w[i] : 0.0;
+        const double run = carry + wave_incl_scan(v);
+        const unsigned long long hit = __ballot(i < hi && run > x);
+        if (hit) return g0 + u * kWave + __ffsll((long long)hit) - 1;
+        carry = __shfl(run, kWave - 1, kWave);
+    }
+    return -2;
+}
+
+// Last point of positive weight in [lo, hi), or -1 (one whole wave).
+__device__ inline int kpp_last_positive(const double* __restrict__ w, int lo, int hi) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int top = hi; top > lo; top -= kWave) {
+        const int i = top - kWave + lane;
+        const bool pos = i >= lo && w[i] > 0.0;
+        const unsigned long long mk = __ballot(pos);
+        if (mk) return top - kWave + 63 - __clzll((long long)mk);
+    }
+    return -1;
+}
+
+// Last point of positive weight in group q of a slice, or -1.
+__device__ inline int kpp_last_positive_group(const double* __restrict__ w, int lo, int hi, int q) {
+    const int g0 = lo + q * kKppGroup;
+    return kpp_last_positive(w, g0, min(hi, g0 + kKppGroup));
+}
+
+// Sum over the LP lanes of a point, which sit 64 / LP lanes apart (lane =
+// j * (64 / LP) + p for point p and dimension chunk j): rotations by 4 and 8
+// within rows of 16 lanes (DPP) and the row swaps by 16 and 32 (permlane),
+// all VALU.  The lanes of a point may differ in the last bit; the value of
+// chunk 0's lane is the one used.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int LP>
+__device__ __forceinline__ double point_sum(double v) {
+    static_assert(LP == 1 || LP == 2 || LP == 4 || LP == 8 || LP == 16, "lanes per point");
+    if constexpr (LP == 16) v += dpp_f64<0x124>(v);  // row_ror:4
+    if constexpr (LP >= 8) v += dpp_f64<0x128>(v);   // row_ror:8
+    if constexpr (LP >= 4) v = pair_sum<16>(v);
+    if constexpr (LP >= 2) v = pair_sum<32>(v);
+    return v;
+}
+
+// One pass over the slice [lo, hi) of a sample (rows sg, stride D): for each
+// point and candidate t < NC the would-be weight nd_t = min(|x - c_t|^2, D^2)
+// (D^2 from `in`; without `in` the distance itself) goes to out[t]; the sums
+// of nd_t per group of 256 points go to gto[t] (LDS) and this thread's share
+// of the slice sums is added to pot[t].
+//
+// Layout: LP = D / 8 lanes per point, each with 8 coordinates; a tile is
+// 64 / LP consecutive points.  A lane holds its 8 coordinates of every
+// candidate (FP64) in registers for the whole pass, so the pass reads no
+// LDS; the rows of the next two tiles are in flight while one is processed.
+template <int D, int NT, int NC>
+__device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const double* crow,
+                           const double* __restrict__ in, bool first, double* const (&out)[4],
+                           double* const (&gto)[4], double (&pot)[4]) {
+    constexpr int NW = NT / kWave;
+    constexpr int LP = D / 8, PPT = kWave / LP, TPG = kKppGroup / PPT;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int p = lane % PPT, j = lane / PPT;  // point within the tile, dimension chunk
+    const int ng = (hi - lo + kKppGroup - 1) / kKppGroup;
+    if (wid >= ng) return;
+    double cr[NC][8];
+#pragma unroll
+    for (int t = 0; t < NC; ++t)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cr[t][u] = crow[t * D + 8 * j + u];
+    // the wave's tiles in order: tile f is tile f % TPG of group wid + NW * (f / TPG)
+    const int nt = ((ng - 1 - wid) / NW + 1) * TPG;
+    auto point = [&](int f) { return lo + (wid + NW * (f / TPG)) * kKppGroup + (f % TPG) * PPT + p; };
+    // branch-free loads (tiles past the wave's last and points past the
+    // slice end re-read the last ones), so that the compiler's wait for a
+    // tile's rows leaves the next tiles' loads in flight
+    auto fetch = [&](int f, float4 (&x)[2], double& dd) {
+        const int i = point(min(f, nt - 1));
+        const int ic = min(i, hi - 1);
+        const float4* r = reinterpret_cast<const float4*>(sg + (size_t)ic * D + 8 * j);
+        x[0] = r[0];
+        x[1] = r[1];
+        dd = in[ic];
+    };
+    double gp[NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) gp[t] = 0.0;
+    auto process = [&](int f, const float4 (&x)[2], double dd) {
+        if (first) dd = __builtin_huge_val();  // the first centre: D^2 is the distance
+        const int i = point(f);
+        const bool mine = i < hi && j == 0;  // the lane that stores and counts the point
+        const double xv[8] = {x[0].x, x[0].y, x[0].z, x[0].w, x[1].x, x[1].y, x[1].z, x[1].w};
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double e = xv[u] - cr[t][u];
+                acc = __fma_rn(e, e, acc);
+            }
+            acc = point_sum<LP>(acc);
+            const double nd = acc < dd ? acc : dd;
+            if (mine) out[t][i] = nd;
+            gp[t] += mine ? nd : 0.0;
+        }
+        if (f % TPG == TPG - 1) {  // last tile of a group: its sums
+            const int q = wid + NW * (f / TPG);
+#pragma unroll
+            for (int t = 0; t < NC; ++t) {
+                const double gs = wave_sum(gp[t]);
+                if (lane == 0) gto[t][q] = gs;
+                pot[t] += lane == 0 ? gs : 0.0;
+                gp[t] = 0.0;
+            }
+        }
+    };
+    // three register buffers, unrolled by three (no buffer copies); nt is
+    // a multiple of TPG >= 4
+    float4 xa[2], xb[2], xc[2];
+    double da, db, dc;
+    fetch(0, xa, da);
+    fetch(1, xb, db);
+    for (int f = 0; f < nt; f += 3) {
+        fetch(f + 2, xc, dc);
+        process(f, xa, da);
+        if (f + 1 >= nt) break;
+        fetch(f + 3, xa, da);
+        process(f + 1, xb, db);
+        if (f + 2 >= nt) break;
+        fetch(f + 4, xb, db);
+        process(f + 2, xc, dc);
+    }
+}
+
+// kpp_stream with the candidate count as a compile-time constant.
+template <int D, int NT>
+__device__ __forceinline__ void kpp_stream_n(int nc, const float* __restrict__ sg, int lo, int hi,
+                                             const double* crow, const double* __restrict__ in,
+                                             double* const (&out)[4], double* const (&gto)[4],
+                                             double (&pot)[4]) {
+    switch (nc) {
+        case 1: kpp_stream<D, NT, 1>(sg, lo, hi, crow, in, false, out, gto, pot); break;
+        case 2: kpp_stream<D, NT, 2>(sg, lo, hi, crow, in, false, out, gto, pot); break;
+        case 3: kpp_stream<D, NT, 3>(sg, lo, hi, crow, in, false, out, gto, pot); break;
+        default: kpp_stream<D, NT, 4>(sg, lo, hi, crow, in, false, out, gto, pot); break;
+    }
+}
+
+// Cold samples of a batch, one per team of `team` workgroups (see above).
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
+    constexpr int NW = NT / kWave;
+    static_assert(NW >= 4, "one wave per candidate in the search");
+    extern __shared__ __align__(16) char smem[];
+    double* gt = reinterpret_cast<double*>(smem);                    // kKppBuffers x ngmax
+    double* crow = gt + (size_t)kKppBuffers * a.ngmax;               // 4 x D
+    double* red = crow + 4 * D;                                      // 4 x NW
+    double* wts = red + 4 * NW;                   // the slices' weights, team order
+    double* tsl = wts + kMaxTeam;                 // the team's slots of one exchange
+    double* pv = tsl + kMaxTeam * kTeamSlot;      // the candidates' potentials
+    int* picks = reinterpret_cast<int*>(pv + 8);                     // kmax
+    int* ints = picks + ((size_t)a.kmax * 4 + 15) / 16 * 4;          // 64
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int T = a.team;
+    const int tau = blockIdx.x % a.n_teams, b = blockIdx.x / a.n_teams;
+    int32_t* const flags = a.tflag + 4 * tau;
+    double* const xs = a.tx + (size_t)tau * 2 * T * kTeamSlot;
+    const int d = a.d;
+    int ebar = 0;  // team barriers passed
+
+    // publish-fence-arrive-wait; every thread returns whether the team is
+    // still alive
+    auto team_sync = [&]() -> bool {
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) ints[1] = team_barrier(flags, T, ebar) ? 1 : 0;
+        __syncthreads();
+        ++ebar;
+        const bool ok = __builtin_amdgcn_readfirstlane(ints[1]) != 0;
+        __threadfence();
+        return ok;
+    };
+    auto slot = [&](int par, int member) { return xs + ((size_t)par * T + member) * kTeamSlot; };
+    // the team's slots of parity par into LDS, one load per thread
+    auto gather_slots = [&](int par) {
+        for (int e = tid; e < T * kTeamSlot; e += NT) tsl[e] = slot(par, e / kTeamSlot)[e % kTeamSlot];
+        __syncthreads();
+    };
+
+    for (int it = 0;; ++it) {
+        int task;
+        if (T == 1) {
+            if (tid == 0) ints[0] = it == 0 ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(a.queue, 1);
+            __syncthreads();
+            task = __builtin_amdgcn_readfirstlane(ints[0]);
+            __syncthreads();
+        } else {
+            task = tau + it * a.n_teams;
+        }
+        if (task >= a.n_samples) break;
+        const int sidx = a.order ? a.order[task] : task;
+        const hpc_sample_desc ds = a.desc[sidx];
+        const int s = ds.s, k = ds.k;
+        // cold: every row degenerate (the same answer in every workgroup)
+        int warm = 0;
+        for (int j = tid; j < k; j += NT) {
+            const float v = a.C[ds.c_offset + (int64_t)j * d];
+            warm |= v == v;
+        }
+        if (__syncthreads_or(warm)) continue;
+
+        // this workgroup's slice: whole groups of 256 points
+        const int per = ((s + T - 1) / T + kKppGroup - 1) / kKppGroup * kKppGroup;
+        const int lo = min(s, b * per), hi = min(s, lo + per);
+        const int ngr = (hi - lo + kKppGroup - 1) / kKppGroup;
+        float* const sg = a.sbuf + (size_t)ds.idx_offset * D;
+        double* const wb = a.d2buf + (size_t)kKppBuffers * ds.idx_offset;
+        auto buf = [&](int j) { return wb + (size_t)j * s; };
+        auto gts = [&](int j) { return gt + (size_t)j * a.ngmax; };
+        const int64_t* const ix = a.idx + ds.idx_offset;
+
+        // gather the slice's rows (zero padded to D); an index outside
+        // [0, m) reads a row of zeros
+        {
+            constexpr int NCH = D / 4;
+            const int total = (hi - lo) * NCH;
+            for (int base = tid; base < total; base += 8 * NT) {
+                float4 v[8];
+                int dst[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = base + u * NT;
+                    dst[u] = -1;
+                    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (e < total) {
+                        const int i = lo + e / NCH, col = (e % NCH) * 4;
+                        const int64_t row = ix[i];
+                        dst[u] = i * D + col;
+                        if (row >= 0 && row < a.m && col < d) {
+                            const float* src = a.X + row * d + col;
+                            if (a.vec4) {
+                                v[u] = *reinterpret_cast<const float4*>(src);
+                            } else {
+                                v[u].x = src[0];
+                                v[u].y = col + 1 < d ? src[1] : 0.f;
+                                v[u].z = col + 2 < d ? src[2] : 0.f;
+                                v[u].w = col + 3 < d ? src[3] : 0.f;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (dst[u] >= 0) *reinterpret_cast<float4*>(sg + dst[u]) = v[u];
+            }
+        }
+        // candidate rows into LDS as FP64, read from X through the indices
+        // (X is never written, so no exchange is needed to see them)
+        auto load_rows = [&](const int (&cand)[4], int nc) {
+            for (int e = tid; e < 4 * D; e += NT) {
+                const int t = e / D, col = e % D;
+                double v = 0.0;
+                if (t < nc && col < d) {
+                    const int ct = t == 0 ? cand[0] : t == 1 ? cand[1] : t == 2 ? cand[2] : cand[3];
+                    const int64_t row = ix[ct];
+                    if (row >= 0 && row < a.m) v = (double)a.X[row * d + col];
+                }
+                crow[e] = v;
+            }
+        };
+
+        // the first centre: uniform over the sample (block 0, word 0)
+        const Words4 w0 = philox_block(ds.seed, a.tag, 0, ds.sample_id, a.call_id);
+        const int i0 = (int)bounded_index(w0.w[0], (uint64_t)s);
+        if (tid == 0) picks[0] = i0;
+        {
+            const int c0[4] = {i0, i0, i0, i0};
+            load_rows(c0, 1);
+        }
+        __syncthreads();
+        double pot[4] = {0.0, 0.0, 0.0, 0.0};
+        {
+            double* const o[4] = {buf(0), buf(0), buf(0), buf(0)};
+            double* const g[4] = {gts(0), gts(0), gts(0), gts(0)};
+            kpp_stream<D, NT, 1>(sg, lo, hi, crow, buf(0), true, o, g, pot);
+        }
+        // this slice's total weight, then every slice's (team order)
+        auto block_pot = [&](double (&v)[4]) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double ws = wave_sum(v[t]);
+                if (lane == 0) red[t * NW + wid] = ws;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                double acc = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) acc += red[t * NW + w];
+                v[t] = acc;
+            }
+            __syncthreads();
+        };
+        block_pot(pot);
+        int cur = 0;
+        int par = 0;
+        bool alive = true;
+        // every slice's weight in team order, in LDS (the same values in
+        // every workgroup of the team)
+        if (T > 1) {
+            if (tid == 0) slot(par, b)[0] = pot[0];
+            alive = team_sync();
+            if (alive) {
+                gather_slots(par);
+                if (tid < T) wts[tid] = tsl[tid * kTeamSlot];
+            }
+        } else if (tid == 0) {
+            wts[0] = pot[0];
+        }
+        __syncthreads();
+        for (int r = 1; r < k && alive; ++r) {
+            const Words4 w = philox_block(ds.seed, a.tag, (uint64_t)r, ds.sample_id, a.call_id);
+            // W and this slice's offset, in team order
+            double W = 0.0, off = 0.0;
+            int last_pos = -1;
+            for (int q = 0; q < T; ++q) {
+                const double v = wts[q];
+                if (q == b) off = W;
+                if (v > 0.0) last_pos = q;
+                W += v;
+            }
+            int pick;
+            if (!(W > 0.0)) {
+                pick = (int)bounded_index(w.w[0], (uint64_t)s);
+            } else {
+                // the targets this slice holds: wave t searches target t
+                const int nc = a.n_cand;
+                const double* const wcur = buf(cur);
+                if (wid < nc) {
+                    const double x = unit_double(w.w[wid]) * W;
+                    // owner: the first slice whose running end exceeds x, or
+                    // (x rounded up to W) the last slice of positive weight
+                    double run = 0.0;
+                    int owner = -1;
+                    for (int q = 0; q < T; ++q) {
+                        run += wts[q];
+                        if (run > x) {
+                            owner = q;
+                            break;
+                        }
+                    }
+                    int found = -1;
+                    if (owner == b) {
+                        found = kpp_find(gts(cur), ngr, wcur, lo, hi, off, x);
+                        if (found == -2) {
+                            // in a group by its sum, in none of its points by
+                            // theirs: the group's last point of positive weight
+                            double c2 = off;
+                            int q2 = 0;
+                            for (; q2 < ngr; ++q2) {
+                                if (c2 + gts(cur)[q2] > x) break;
+                                c2 += gts(cur)[q2];
+                            }
+                            found = kpp_last_positive_group(wcur, lo, hi, min(q2, ngr - 1));
+                        }
+                        if (found == -1) found = kpp_last_positive(wcur, lo, hi);
+                    } else if (owner < 0 && last_pos == b) {
+                        found = kpp_last_positive(wcur, lo, hi);
+                    }
+                    if (lane == 0) ints[8 + wid] = found;
+                }
+                __syncthreads();
+                // the candidates: each target's point from the slice that
+                // holds it
+                if (T > 1) {
+                    par ^= 1;
+                    if (tid < 4) slot(par, b)[4 + tid] = (double)(tid < nc ? ints[8 + tid] : -1);
+                    alive = team_sync();
+                    if (!alive) break;
+                    gather_slots(par);
+                    if (tid < 4) {
+                        int c = -1;
+                        for (int q = 0; q < T; ++q) {
+                            const int v = (int)tsl[q * kTeamSlot + 4 + tid];
+                            c = v > c ? v : c;
+                        }
+                        ints[12 + tid] = c < 0 ? 0 : c;
+                    }
+                } else if (tid < 4) {
+                    ints[12 + tid] = ints[8 + tid] < 0 ? 0 : ints[8 + tid];
+                }
+                __syncthreads();
+                const int cand[4] = {ints[12], ints[13], ints[14], ints[15]};
+                load_rows(cand, nc);
+                __syncthreads();
+                // the candidates' would-be weights into the four buffers
+                // other than the current one
+                double* o[4];
+                double* g[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int j = (cur + 1 + t) % kKppBuffers;
+                    o[t] = buf(j);
+                    g[t] = gts(j);
+                }
+                double pt[4] = {0.0, 0.0, 0.0, 0.0};
+                kpp_stream_n<D, NT>(nc, sg, lo, hi, crow, wcur, o, g, pt);
+                block_pot(pt);
+                // the potentials (slice sums added in team order) and the
+                // kept candidate; its slice sums are the next weights
+                if (T > 1) {
+                    par ^= 1;
+                    if (tid < 4) slot(par, b)[tid] = pt[tid];
+                    alive = team_sync();
+                    if (!alive) break;
+                    gather_slots(par);
+                    if (tid < 4) {
+                        double acc = 0.0;
+                        for (int q = 0; q < T; ++q) acc += tsl[q * kTeamSlot + tid];
+                        pv[tid] = acc;
+                    }
+                } else if (tid < 4) {
+                    pv[tid] = pt[tid];
+                }
+                __syncthreads();
+                int tb = 0;
+#pragma unroll
+                for (int t = 1; t < 4; ++t)
+                    if (t < nc && pv[t] < pv[tb]) tb = t;
+                pick = cand[tb];
+                cur = (cur + 1 + tb) % kKppBuffers;
+                __syncthreads();  // every thread has read pv and wts
+                if (T > 1) {
+                    if (tid < T) wts[tid] = tsl[tid * kTeamSlot + tb];
+                } else if (tid == 0) {
+                    wts[0] = pt[tb];
+                }
+                __syncthreads();
+            }
+            if (tid == 0) picks[r] = pick;
+        }
+        __syncthreads();
+        if (!alive) return;  // the team gave up: its remaining samples stay cold
+        // the first workgroup writes the seeded rows (copies of sample rows)
+        if (b == 0) {
+            for (int e = tid; e < k * d; e += NT) {
+                const int j = e / d, col = e % d;
+                const int64_t row = ix[picks[j]];
+                a.C[ds.c_offset + e] = (row >= 0 && row < a.m) ? a.X[row * d + col] : 0.f;
+            }
+            if (a.chosen)
+                for (int j = tid; j < k; j += NT) a.chosen[j] = picks[j];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace hpc

@@ -591,6 +591,9 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             for (int j = tid; j < k; j += NT) deg |= L.C64[j * CS] != L.C64[j * CS];
             return block_any<NT>(deg != 0, L.ints + 16);
         };
+        // seeding only: a block with no degenerate row (seeded already by
+        // the team kernel, or all valid) is left as it is
+        if (a.seed_only && !any_degenerate()) continue;
         const bool direct_ok = !a.seed_only && a.vec4 && d == D;
         bool gathered = !direct_ok || any_degenerate();
         // a sample is shared only while it reads its rows straight from X
@@ -607,9 +610,6 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         if (gathered) gather();
 
         if (a.seed_only) {
-            if (a.chosen)
-                for (int j = tid; j < k; j += NT) a.chosen[j] = -1;
-            __syncthreads();
             kmeanspp_wg<D, NT, PREC>(sv, s, k, a.n_cand, d2, ds.seed, kTagSeed, ds.sample_id,
                                      a.call_id, a.chosen, L);
         } else {

@@ -45,7 +45,7 @@ def tuned(plan, X, idx, C, *, path: str | None = None, max_iter: int = 3, retune
     db = load(path)
     ent = db.get(key)
     if ent is not None and not retune:
-        cfg = {k: int(ent[k]) for k in ("wg_per_cu", "copies", "order")}
+        cfg = {k: int(ent.get(k, 0)) for k in ("wg_per_cu", "copies", "order", "seed_team", "seed_inflight")}
         plan.set_tune(**cfg)
         return cfg, None
     t, ms = plan.autotune(X, idx, C, max_iter=max_iter)

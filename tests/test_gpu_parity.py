@@ -222,6 +222,42 @@ def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed, prec):
     assert clean >= 5, "too few clean seeds"
 
 
+@pytest.mark.parametrize("team", [1, 2, 4, 8])
+@pytest.mark.parametrize("d,s,k", [(8, 3000, 10), (32, 10_000, 25), (64, 6000, 40)])
+def test_cold_batch_seeding_teams(hp, orc, team, d, s, k):
+    """Cold samples seeded by teams of 1, 2, 4 and 8 workgroups (a plan's
+    seed_team), then Lloyd to the stop rule: pass counts, objectives,
+    centroids and labels against the oracle's cold start on the same
+    streams."""
+    m = 60_000
+    Xn, Xg = _mix(m, d, 12, seed=500 + d)
+    W = 4
+    desc, idx_len, c_len = hp.make_desc([s] * W, [k] * W, seed=21, sample_id=np.arange(W), d=d)
+    with hp.Plan(d, desc, idx_len, c_len) as plan:
+        plan.set_tune(seed_team=team)
+        assert plan.tune.seed_team == team
+        idx = torch.empty(idx_len, dtype=torch.int64, device="cuda")
+        plan.draw(m, idx)
+        C = torch.full((c_len,), float("nan"), device="cuda")
+        f, it, lab = plan.lloyd(Xg, idx, C, want_labels=True)
+        torch.cuda.synchronize()
+    Cg, fg, itg, lg = C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()
+    ii = idx.cpu().numpy()
+    clean = 0
+    for b in range(W):
+        ib = ii[b * s:(b + 1) * s]
+        assert np.array_equal(ib, orc.draw_sample(m, s, 21, b))
+        ro = orc.lloyd(Xn, ib, k, seed=21, sample_id=b, want_margins=True)
+        if not diag_clean(ro.diag):
+            continue
+        clean += 1
+        assert itg[b] == ro.iters, (team, b, itg[b], ro.iters)
+        assert rel(fg[b], ro.f) <= F_REL
+        assert_centroids(Cg[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, Xn[ib])
+        assert_labels(lg[b * s:(b + 1) * s], ro.labels, ro.margins)
+    assert clean >= 3, f"only {clean} of {W} samples compared"
+
+
 def test_lloyd_reseeds_emptied_cluster(hp, orc):
     """A centroid far from every point empties in pass 1 and is re-seeded
     (stream RESEED, call 1) at the top of pass 2."""
