@@ -250,7 +250,10 @@ def measure(api, X, args, copy, other_precision):
         "cold_sample": cold_sample_latency(api, X, s, k, prec, args.seed),
     }
     if main_res["check"] is not None:
-        out["error_vs_oracle"] = error_report(api, X, main_res["check"], args, m, d, s, k, prec)
+        # (the oracle's objective over the sampled rows is one thread's work:
+        # fewer rows for the wide workload)
+        out["error_vs_oracle"] = error_report(api, X, main_res["check"], args, m, d, s, k, prec,
+                                              sse_rows=1_000_000 if k * d <= 1000 else 200_000)
     if others:
         out["other_screenings"] = {
             name: {"dtype": SCREENINGS[name][1],
@@ -669,18 +672,10 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
         res["f_ref_source"] = "oracle"
     res["f_ref"] = f_ref
     target = f_ref * (1 + 1e-3)
-    # a second, tighter threshold: the quality of the oracle's 64-sample run
-    # itself (within the SSE tolerance), which the plain form reaches only
-    # after its best sample and a batched round may reach at once
-    target2 = f_ref * (1 + 1e-6)
-    res["threshold2_rel"] = 1e-6
     sses = _sses(api, X, hist, api.PREC_FP32)
     i, t, v = _first_reach(sses, t_plain, target)
-    i2, t2, _ = _first_reach(sses, t_plain, target2)
     res["plain_fp32_per_sample"] = {"ms": t, "samples": None if i is None else i + 1,
-                                    "sse": v, "ms_all": t_plain[-1],
-                                    "ms_threshold2": t2,
-                                    "samples_threshold2": None if i2 is None else i2 + 1}
+                                    "sse": v, "ms_all": t_plain[-1]}
 
     model = None
     if args.train_pairs > 0:
@@ -738,9 +733,7 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
         times = [evs[0].elapsed_time(e) for e in evs[1:]]
         sses = _sses(api, X, hist, prec)
         i, t, v = _first_reach(sses, times, target)
-        i2, t2, _ = _first_reach(sses, times, target2)
         res[name] = {"ms": t, "rounds": None if i is None else i + 1, "sse": v,
-                     "ms_threshold2": t2, "rounds_threshold2": None if i2 is None else i2 + 1,
                      "ms_per_round": [round(x, 3) for x in np.diff([0.0] + times)]}
         if acc is not None:
             res[name]["accepted_frac"] = acc.float().mean().item()
@@ -748,9 +741,6 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
     best = res.get("batched_bf16_learned") or res["batched_bf16"]
     p = res["plain_fp32_per_sample"]["ms"]
     res["speedup_vs_plain"] = (p / best["ms"]) if (p and best["ms"]) else None
-    p2 = res["plain_fp32_per_sample"]["ms_threshold2"]
-    res["speedup_vs_plain_threshold2"] = ((p2 / best["ms_threshold2"])
-                                          if (p2 and best["ms_threshold2"]) else None)
     if model is not None:
         model.close()
     return res

@@ -148,7 +148,10 @@ int hpc_draw_samples(int64_t m, const hpc_sample_desc *desc, int32_t n_samples, 
  *   chosen (device int32[k], nullable): sample-local index of the point given
  *     to each seeded row, -1 for kept rows.
  *   Stream: tag 1, counter (block, sample_id, call_id, 0).
- * Distances, prefix sums and potentials are FP64.
+ * Distances, prefix sums and potentials are FP64.  A cold start is run by a
+ * team of workgroups (one slice of the sample each, one exchange of slice
+ * and group sums per step); a partial one by one workgroup.  The chosen
+ * indices do not depend on the team size: only the order of FP64 sums does.
  * Errors: NULL X/idx/C, s < k, n_candidates outside [1, 4], sizes out of
  * range. */
 int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, int32_t s,
@@ -185,16 +188,21 @@ int hpc_seed_kmeanspp(const float *X, int64_t m, int32_t d, const int64_t *idx, 
  *   f_out (device double[n]), iters_out (device int32[n]); labels_out
  *   nullable (device int32[idx_len]).
  * Samples may be processed in any order and concurrently; each sample's
- * result depends only on its own inputs.  For d > 32, when the GPU holds at
- * least twice as many workgroups as there are samples, a sample that starts
- * with every centroid valid and rows of X 16-byte aligned is worked by two
- * workgroups, each on every other tile of 16 points, which exchange their
- * partial sums once per pass (until a re-seed, the gathered copy or the
- * direct-sum objective is needed; one workgroup finishes the sample).  The
- * results then differ from one workgroup's only in the order of the FP64
- * sums.  A sample whose partner workgroup does not arrive within about a
- * second (not expected: the grid is sized to be resident at once) is
- * abandoned and reports f = NaN and iters_out = -1.
+ * result depends only on its own inputs.  Cold samples (every row
+ * degenerate) are first seeded by a separate kernel, each by a team of
+ * workgroups sized to the free capacity (the same random stream as the
+ * re-seeding above, so the result does not depend on the team).  When the
+ * GPU holds at least twice as many workgroups as there are samples, a
+ * sample that starts with every centroid valid (or was just seeded) and
+ * whose rows of X are 16-byte aligned with d a multiple of the padded width
+ * is worked by P workgroups (P <= 16, at least 1,024 points each), each on
+ * every P-th tile of 16 points, which exchange their partial sums once per
+ * pass (until a re-seed, the gathered copy or the direct-sum objective is
+ * needed; one workgroup finishes the sample).  The results then differ from
+ * one workgroup's only in the order of the FP64 sums.  A sample whose
+ * partner workgroups do not all arrive within about a second (not expected:
+ * the grid is sized to be resident at once) is abandoned and reports
+ * f = NaN and iters_out = -1.
  * Errors: NULL required pointers, max_iter < 1, rel_tol < 0 or NaN, any
  * s < k, offsets beyond idx_len / c_len, unknown precision. */
 int hpc_lloyd_batch(const float *X, int64_t m, int32_t d, const int64_t *idx, int64_t idx_len,

@@ -230,6 +230,14 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsign
         p[i] = v;
 }
 
+// chosen[j] <- tmp[j] where the resident seeding pass picked a point for row
+// j (tmp[j] >= 0); the other rows keep what the team kernel wrote (or -1).
+__global__ void k_merge_chosen(int32_t* __restrict__ chosen, const int32_t* __restrict__ tmp,
+                               int32_t k) {
+    for (int j = threadIdx.x; j < k; j += blockDim.x)
+        if (tmp[j] >= 0) chosen[j] = tmp[j];
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)

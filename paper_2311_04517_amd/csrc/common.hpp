@@ -122,6 +122,27 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return tot;
 }
 
+// Data exchanged between workgroups, stored and loaded as relaxed
+// device-scope atomics: on gfx950 these accesses are coherent across the
+// XCDs' L2 caches by themselves, so an exchange needs no cache write-back or
+// invalidation (which device-scope fences perform on the whole L2).  A
+// writer waits for its stores to complete (wait_stores) before it signals.
+__device__ __forceinline__ void store_dev(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_dev(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void store_dev(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory access this wave issued has completed.
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
 __device__ __forceinline__ bool is_nan_f(float v) { return v != v; }
 
 // FP64 data in LDS addressed as such (32-bit addresses; a generic pointer

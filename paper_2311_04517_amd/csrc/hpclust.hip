@@ -210,23 +210,37 @@ struct ResGeo {
     int copies = 1;      // private partial-sum copies per workgroup
     size_t lds = 0;      // dynamic LDS bytes
     int per_cu_max = 0;  // occupancy limit at this LDS size
-    int split = 1;       // 2: two workgroups per sample (shared warm samples)
+    int split = 1;       // workgroups per sample (P > 1: shared warm samples)
+    bool share = false;  // the kernel form with the shared-sample paths
 };
 
-// Doubles of the pair-exchange buffer for n samples: two halves, two pass
-// parities, and per slot the partial sums (kmax rows of D + 1) and Q.
-size_t xbuf_doubles(int n, int kmax, int D) {
-    return (size_t)n * 4 * ((size_t)kmax * (D + 1) + 8);
+// Doubles of the exchange buffer for n samples of `parts` workgroups: per
+// part two pass parities, and per slot the partial sums (kmax rows of D + 1)
+// and Q.
+size_t xbuf_doubles(int n, int parts, int kmax, int D) {
+    return (size_t)n * parts * 2 * ((size_t)kmax * (D + 1) + 8);
 }
 
-// Launch geometry for a batch of n_wg samples with at most kmax centroids.
-// copies_req 0 = as many private copies as fit in 64 KiB; wg_per_cu 0 = as
-// many workgroups per CU as the occupancy allows.  With allow_split, wide
-// rows (d > 32) and at least twice as many resident workgroups as samples,
-// every sample gets two workgroups (warm samples are then shared).
+// Points a part of a shared sample keeps at least (eight tiles per wave).
+constexpr int kMinPartPoints = 1024;
+
+// The resident kernel's form: up to d = 32 the shared-sample paths live in
+// a separate form; wider rows always have them.
+template <int D>
+constexpr bool share_form(bool shared) {
+    return D >= 64 ? true : shared;
+}
+
+// Launch geometry for a batch of n_wg samples (at most kmax centroids, the
+// smallest s_min points).  copies_req 0 = as many private copies as fit in
+// 64 KiB; wg_per_cu 0 = as many workgroups per CU as the occupancy allows.
+// With max_parts > 1 and at least twice as many resident workgroups (of the
+// shared form) as samples, every sample gets P = min(resident / samples,
+// max_parts, s_min / kMinPartPoints) workgroups (warm samples are then
+// shared).
 template <int D, int PREC>
-int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo* out,
-                      bool allow_split) {
+int resident_geometry(int kmax, int n_wg, int s_min, int wg_per_cu, int copies_req,
+                      int max_parts, ResGeo* out) {
     using S = hpc::Smem<D, kNT, PREC>;
     constexpr int NW = kNT / hpc::kWave;
     int lds_max = 0;
@@ -245,20 +259,42 @@ int resident_geometry(int kmax, int n_wg, int wg_per_cu, int copies_req, ResGeo*
                     "k=%d with padded d=%d and %d partial copies needs %zu bytes of LDS per "
                     "workgroup (limit %d)",
                     kmax, D, copies, lds, lds_max);
-    auto kern = hpc::k_lloyd_resident<D, kNT, PREC>;
-    if (lds > 64 * 1024)
-        HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = 0;
-    HPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kNT, lds));
     int cus = 0;
     rc = device_cus(&cus);
     if (rc) return rc;
-    per_cu = std::max(1, per_cu);
-    const int use = wg_per_cu > 0 ? std::min(per_cu, wg_per_cu) : per_cu;
-    const int64_t cap = (int64_t)cus * use;
-    out->split = (allow_split && D >= 64 && 2 * (int64_t)n_wg <= cap) ? 2 : 1;
-    out->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)n_wg * out->split, cap));
+    // resident workgroups of one form
+    auto capacity = [&](auto kern, int* per_cu_out, int64_t* cap) -> int {
+        if (lds > 64 * 1024)
+            HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int per_cu = 0;
+        HPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kNT, lds));
+        per_cu = std::max(1, per_cu);
+        *per_cu_out = per_cu;
+        *cap = (int64_t)cus * (wg_per_cu > 0 ? std::min(per_cu, wg_per_cu) : per_cu);
+        return HPC_OK;
+    };
+    int per_s = 0;
+    int64_t cap_s = 0;
+    rc = capacity(hpc::k_lloyd_resident<D, kNT, PREC, true>, &per_s, &cap_s);
+    if (rc) return rc;
+    int parts = 1;
+    if (max_parts > 1) {
+        const int64_t by_size = std::max(1, s_min / kMinPartPoints);
+        parts = (int)std::max<int64_t>(
+            1, std::min<int64_t>({cap_s / n_wg, (int64_t)max_parts, (int64_t)hpc::kMaxParts,
+                                  by_size}));
+    }
+    int per_cu = per_s;
+    int64_t cap = cap_s;
+    const bool share = share_form<D>(parts > 1);
+    if (!share) {
+        rc = capacity(hpc::k_lloyd_resident<D, kNT, PREC, share_form<D>(false)>, &per_cu, &cap);
+        if (rc) return rc;
+    }
+    out->split = parts;
+    out->share = share;
+    out->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)n_wg * parts, cap));
     out->copies = copies;
     out->lds = lds;
     out->per_cu_max = per_cu;
@@ -271,22 +307,26 @@ int launch_resident(hpc::LloydArgs a, const ResGeo& g, hipStream_t st) {
     a.n_copies = g.copies;
     a.split = g.split;
     a.xstride = a.kmax * (D + 1) + 8;
-    if (g.split == 2 && (!a.xbuf || !a.xflag))
+    if (g.split > 1 && (!a.xbuf || !a.xflag))
         return fail(HPC_ERR_INVALID_ARG, "shared samples without an exchange buffer");
     hipLaunchKernelGGL(hpc::k_fill_i32, dim3(1), dim3(64), 0, st, a.queue, (int64_t)1, 0);
-    if (g.split == 2)
+    if (g.split > 1)
         hipLaunchKernelGGL(hpc::k_fill_i32, dim3((4 * a.n_samples + 255) / 256), dim3(256), 0, st,
                            a.xflag, (int64_t)4 * a.n_samples, 0);
-    hipLaunchKernelGGL((hpc::k_lloyd_resident<D, kNT, PREC>), dim3(g.grid), dim3(kNT), g.lds, st,
-                       a);
+    if (g.share)
+        hipLaunchKernelGGL((hpc::k_lloyd_resident<D, kNT, PREC, true>), dim3(g.grid), dim3(kNT),
+                           g.lds, st, a);
+    else
+        hipLaunchKernelGGL((hpc::k_lloyd_resident<D, kNT, PREC, share_form<D>(false)>),
+                           dim3(g.grid), dim3(kNT), g.lds, st, a);
     HPC_HIP(hipGetLastError());
     return HPC_OK;
 }
 
-int resident_geo(int D, int prec, int kmax, int n_wg, bool allow_split, ResGeo* g) {
+int resident_geo(int D, int prec, int kmax, int n_wg, int s_min, int max_parts, ResGeo* g) {
     return with_dp(D, prec, [&](auto Dc, auto Pc) {
-        return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(kmax, n_wg, 0, 0, g,
-                                                                           allow_split);
+        return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(kmax, n_wg, s_min, 0, 0,
+                                                                           max_parts, g);
     });
 }
 
@@ -332,7 +372,7 @@ int kpp_geometry(int n, int smax, int kmax, int team_req, int inflight_req, KppG
     auto shape = [&](int T, int* ngmax, size_t* lds, int64_t* cap) -> int {
         const int64_t per = ((smax + (int64_t)T - 1) / T + hpc::kKppGroup - 1) / hpc::kKppGroup;
         *ngmax = (int)std::max<int64_t>(1, per);
-        *lds = hpc::kpp_lds_bytes<D, kKppNT>(*ngmax, kmax);
+        *lds = hpc::kpp_lds_bytes<D, kKppNT>(*ngmax, kmax, T);
         *cap = 0;
         if (*lds > (size_t)lds_max) return HPC_OK;
         if (*lds > 64 * 1024)
@@ -387,10 +427,12 @@ int kpp_geo(int D, int n, int smax, int kmax, int team_req, int inflight_req, Kp
     return fail(HPC_ERR_UNSUPPORTED, "seeding: padded dimension %d", D);
 }
 
-// Bytes of the seeding kernel's team flags and exchange slots for at most
-// `grid` workgroups (one team per workgroup at most).
+// Bytes of the seeding kernel's team flags (four ints per team, at most one
+// team per workgroup) and exchange slots (two parities per workgroup).
 size_t kpp_flag_bytes(int64_t grid) { return (size_t)grid * 16; }
-size_t kpp_slot_bytes(int64_t grid) { return (size_t)grid * 2 * hpc::kTeamSlot * 8; }
+size_t kpp_slot_bytes(const KppGeo& g) {
+    return g.team > 1 ? (size_t)g.grid * 2 * hpc::kpp_slot_doubles(g.ngmax) * 8 : 0;
+}
 
 // Enqueue the flag resets and the seeding kernel (kernel launches only).
 int launch_kpp(int D, hpc::KppArgs a, const KppGeo& g, hipStream_t st) {
@@ -596,22 +638,25 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     if (rc) return rc;
     const int D = pad_dim(d);
     ResGeo g;
-    rc = resident_geo(D, precision, kmax, n, !seed_only, &g);
+    int s_min = INT32_MAX;
+    for (int32_t b = 0; b < n; ++b) s_min = std::min(s_min, desc[b].s);
+    rc = resident_geo(D, precision, kmax, n, s_min, seed_only ? 1 : hpc::kMaxParts, &g);
     if (rc) return rc;
     const std::vector<int32_t> order = longest_first(desc, n);
     const size_t desc_b = (size_t)n * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n * 4;
     const size_t sbuf_b = (size_t)idx_len * D * 4;
-    const size_t xbuf_b = g.split == 2 ? xbuf_doubles(n, kmax, D) * 8 : 0;
-    const size_t xflag_b = g.split == 2 ? (size_t)n * 16 : 0;
+    const size_t xbuf_b = g.split > 1 ? xbuf_doubles(n, g.split, kmax, D) * 8 : 0;
+    const size_t xflag_b = g.split > 1 ? (size_t)n * 16 : 0;
     int smax = 0;
     for (int32_t b = 0; b < n; ++b) smax = std::max(smax, desc[b].s);
     KppGeo kg;
     rc = kpp_geo(D, n, smax, kmax, 0, 0, &kg);
     if (rc) return rc;
-    const size_t kflag_b = kpp_flag_bytes(kg.grid), kslot_b = kpp_slot_bytes(kg.grid);
+    const size_t kflag_b = kpp_flag_bytes(kg.grid), kslot_b = kpp_slot_bytes(kg);
     const size_t need = Carve::need({desc_b + order_b, 256, sbuf_b, (size_t)idx_len * 40,
-                                     (size_t)idx_len * 4, xbuf_b, xflag_b, kflag_b, kslot_b});
+                                     (size_t)idx_len * 4, xbuf_b, xflag_b, kflag_b, kslot_b,
+                                     (size_t)kmax * 4});
     rc = ws_reserve_dev(w, need);
     if (rc) return rc;
     Carve cv(w->dev);
@@ -624,6 +669,7 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     int32_t* xflag = static_cast<int32_t*>(cv.take(xflag_b));
     int32_t* kflag = static_cast<int32_t*>(cv.take(kflag_b));
     double* kslot = static_cast<double*>(cv.take(kslot_b));
+    int32_t* chosen_tmp = static_cast<int32_t*>(cv.take((size_t)kmax * 4));
     std::vector<char> host(desc_b + order_b);
     memcpy(host.data(), desc, desc_b);
     memcpy(host.data() + desc_b, order.data(), order_b);
@@ -653,19 +699,30 @@ int run_resident(const float* X, int64_t m, int32_t d, const int64_t* idx, int64
     a.call_id = call_id;
     a.chosen = chosen;
     a.vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-    a.xbuf = g.split == 2 ? xbuf : nullptr;
-    a.xflag = g.split == 2 ? xflag : nullptr;
+    a.xbuf = g.split > 1 ? xbuf : nullptr;
+    a.xflag = g.split > 1 ? xflag : nullptr;
     // cold samples are seeded first by the team kernel (stream tag SEED and
     // the caller's call_id for the seeding call; RESEED and 0, the stream of
     // a Lloyd cold start, otherwise); the resident kernel then seeds only
     // what is left: partially valid blocks, or samples of a team that gave up
+    // (the seeding call: the team kernel writes the caller's chosen for a
+    // cold start; the resident kernel, which resets chosen to -1 for every
+    // block it visits, writes a scratch copy that is merged afterwards)
     if (seed_only && chosen)
         hipLaunchKernelGGL(hpc::k_fill_i32, dim3(1), dim3(256), 0, st, chosen, (int64_t)kmax, -1);
     const hpc::KppArgs ka = kpp_args(a, seed_only ? hpc::kTagSeed : hpc::kTagReseed,
                                      seed_only ? call_id : 0u, n_cand, queue + 16, kflag, kslot);
     rc = launch_kpp(D, ka, kg, st);
     if (rc) return rc;
-    return dispatch_resident(D, precision, a, g, st);
+    if (seed_only && chosen) a.chosen = chosen_tmp;
+    rc = dispatch_resident(D, precision, a, g, st);
+    if (rc) return rc;
+    if (seed_only && chosen) {
+        hipLaunchKernelGGL(hpc::k_merge_chosen, dim3(1), dim3(256), 0, st, chosen,
+                           (const int32_t*)chosen_tmp, (int32_t)kmax);
+        HPC_HIP(hipGetLastError());
+    }
+    return HPC_OK;
 }
 
 int next_pow2(int64_t v) {
@@ -684,6 +741,7 @@ struct hpc_plan_s {
     int64_t idx_len = 0, c_len = 0;
     std::vector<hpc_sample_desc> desc;
     char* mem = nullptr;
+    void* kmem = nullptr;  // the seeding teams' flags and exchange slots
     hpc_sample_desc* desc_dev = nullptr;   // live table (sample ids advance)
     hpc_sample_desc* desc_init = nullptr;  // table as created
     int32_t* order_dev = nullptr;          // [0, n): longest first; [n, 2n): given order
@@ -699,7 +757,8 @@ struct hpc_plan_s {
     int32_t* kflag = nullptr;  // seeding teams' flags and exchange slots
     double* kslot = nullptr;
     int64_t kgrid_max = 0;     // workgroups those buffers serve
-    int smax = 0;
+    int smax = 0, smin = 0;
+    int xparts = 1;            // workgroups per shared sample the exchange buffer serves
     hpc_tune tune{};
     ResGeo geo;
     KppGeo kgeo;
@@ -719,15 +778,16 @@ int plan_check(hpc_plan p, const char* where) {
     return HPC_OK;
 }
 
-int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g, bool allow_split) {
+int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g, int max_parts) {
     return with_dp(p->D, p->prec, [&](auto Dc, auto Pc) {
         return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(
-            p->kmax, p->n, t.wg_per_cu, t.copies, g, allow_split);
+            p->kmax, p->n, p->smin, t.wg_per_cu, t.copies, max_parts, g);
     });
 }
 
+// Geometry within the plan's exchange buffer (its parts per sample).
 int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g) {
-    return plan_geometry(p, t, g, p->xbuf != nullptr);
+    return plan_geometry(p, t, g, p->xparts);
 }
 
 hpc::LloydArgs plan_args(hpc_plan p, const float* X, int64_t m, const int64_t* idx, float* C,
@@ -1096,32 +1156,48 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     p->desc.assign(desc, desc + n_samples);
     auto cleanup = [&](int code) {
         if (p->mem) (void)hipFree(p->mem);
+        if (p->kmem) (void)hipFree(p->kmem);
         delete p;
         return code;
     };
     if (hipGetDevice(&p->device) != hipSuccess)
         return cleanup(fail(HPC_ERR_HIP, "hpc_plan_create: hipGetDevice failed"));
     // samples can be shared only if the default geometry (the most
-    // workgroups per CU) shares them; then the exchange buffers are made
+    // workgroups per CU) shares them; then the exchange buffers are made for
+    // its parts per sample, the most any configuration of this plan uses
+    p->smin = INT32_MAX;
+    for (int32_t b = 0; b < n_samples; ++b) p->smin = std::min(p->smin, desc[b].s);
     ResGeo g0;
-    rc = plan_geometry(p, p->tune, &g0, true);
+    rc = plan_geometry(p, p->tune, &g0, hpc::kMaxParts);
     if (rc) return cleanup(rc);
-    const bool shareable = g0.split == 2;
+    const bool shareable = g0.split > 1;
+    p->xparts = g0.split;
     const size_t desc_b = (size_t)n_samples * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n_samples * 8;
     const size_t sbuf_b = (size_t)idx_len * p->D * 4;
     const size_t d2_b = (size_t)idx_len * 40;  // D^2 and up to four candidate distances
-    const size_t xbuf_b = shareable ? xbuf_doubles(n_samples, kmax, p->D) * 8 : 0;
+    const size_t xbuf_b = shareable ? xbuf_doubles(n_samples, p->xparts, kmax, p->D) * 8 : 0;
     const size_t xflag_b = shareable ? (size_t)n_samples * 16 : 0;
     for (int32_t b = 0; b < n_samples; ++b) p->smax = std::max(p->smax, desc[b].s);
     int cus = 0;
     rc = device_cus(&cus);
     if (rc) return cleanup(rc);
     p->kgrid_max = (int64_t)cus * kKppMaxWgPerCu;
-    const size_t kflag_b = kpp_flag_bytes(p->kgrid_max), kslot_b = kpp_slot_bytes(p->kgrid_max);
+    // the seeding teams' exchange slots for the largest team form this plan
+    // can be given (any seed_team), so a later set_tune never allocates
+    size_t kslot_b = 0;
+    for (int T = 2; T <= kKppMaxTeam; ++T) {
+        KppGeo kg;
+        rc = kpp_geo(p->D, n_samples, p->smax, kmax, T, 0, &kg);
+        if (rc) return cleanup(rc);
+        kslot_b = std::max(kslot_b, kpp_slot_bytes(kg));
+    }
+    const size_t kflag_b = kpp_flag_bytes(p->kgrid_max);
+    // (in an allocation of their own: the layout of the rest is the one the
+    // Lloyd kernels were measured with)
     const size_t need = Carve::need({desc_b, desc_b, order_b, 256, sbuf_b, d2_b, (size_t)idx_len * 4,
                                      (size_t)c_len * 4, (size_t)n_samples * 8,
-                                     (size_t)n_samples * 4, xbuf_b, xflag_b, kflag_b, kslot_b});
+                                     (size_t)n_samples * 4, xbuf_b, xflag_b});
     hipError_t e = hipMalloc(&p->mem, need);
     if (e != hipSuccess) {
         p->mem = nullptr;
@@ -1146,8 +1222,15 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
         (void)cv.take(xbuf_b);
         (void)cv.take(xflag_b);
     }
-    p->kflag = static_cast<int32_t*>(cv.take(kflag_b));
-    p->kslot = static_cast<double*>(cv.take(kslot_b));
+    e = hipMalloc(&p->kmem, Carve::need({kflag_b, kslot_b}));
+    if (e != hipSuccess) {
+        p->kmem = nullptr;
+        return cleanup(fail(HPC_ERR_NO_MEMORY, "hpc_plan_create: seeding buffers: %s",
+                            hipGetErrorString(e)));
+    }
+    Carve ck(p->kmem);
+    p->kflag = static_cast<int32_t*>(ck.take(kflag_b));
+    p->kslot = static_cast<double*>(ck.take(kslot_b));
     std::vector<int32_t> orders = longest_first(desc, n_samples);
     orders.resize((size_t)2 * n_samples);
     std::iota(orders.begin() + n_samples, orders.end(), 0);
@@ -1172,6 +1255,7 @@ int hpc_plan_destroy(hpc_plan plan) {
     if (plan->exec) HPC_HIP(hipGraphExecDestroy(plan->exec));
     if (plan->cap) HPC_HIP(hipStreamDestroy(plan->cap));
     if (plan->mem) HPC_HIP(hipFree(plan->mem));
+    if (plan->kmem) HPC_HIP(hipFree(plan->kmem));
     delete plan;
     HPC_HIP(hipSetDevice(prev));
     return HPC_OK;

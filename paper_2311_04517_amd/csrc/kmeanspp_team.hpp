@@ -36,9 +36,13 @@
 // search to one group of 256 weights.
 //
 // Exchanges: per team a monotonic arrival counter and per workgroup a slot
-// of eight doubles (two step parities); a workgroup publishes its slot,
-// fences it at device scope, counts its arrival and waits for the whole
-// team, within a bounded spin.  A team that runs out of the spin (not
+// (two step parities); a workgroup publishes its slot, waits for its stores
+// to complete, counts its arrival and waits for the whole team, within a
+// bounded spin.  Everything one workgroup reads from another (slots, the
+// weights of a group) is stored and loaded as relaxed device-scope atomics,
+// which are coherent across the XCDs' caches without fences: a device-scope
+// fence writes back or invalidates a whole L2, which at every exchange of
+// every team would cost all workgroups on that XCD their cached data.  A team that runs out of the spin (not
 // expected: the host launches a team form only when every workgroup of the
 // grid is resident at once) gives up: its workgroups leave the kernel and
 // the rows of the samples it has not finished stay degenerate, which the
@@ -52,7 +56,6 @@ namespace hpc {
 constexpr int kKppGroup = 256;            // points per group sum (four tiles of 64)
 constexpr int kKppBuffers = 5;            // rotating D^2 buffers per sample
 constexpr int kTeamSpinLimit = 1 << 20;   // about a second of waiting per exchange
-constexpr int kTeamSlot = 8;              // doubles per workgroup slot and parity
 
 struct KppArgs {
     const float* X;
@@ -76,26 +79,22 @@ struct KppArgs {
     int32_t kmax;
     int32_t* queue;        // next task for T == 1 (zeroed per launch)
     int32_t* tflag;        // per team: arrivals, abort (zeroed per launch)
-    double* tx;            // per team 2 * T slots of kTeamSlot doubles
+    double* tx;            // per team 2 * T slots of kpp_slot_doubles(ngmax) doubles
 };
 
 constexpr int kMaxTeam = 64;               // workgroups per team at most
 
-template <int D, int NT>
-__host__ __device__ inline size_t kpp_lds_bytes(int ngmax, int kmax) {
-    return (size_t)kKppBuffers * ngmax * 8 + 4 * (size_t)D * 8 + 4 * (NT / kWave) * 8 +
-           (size_t)kMaxTeam * 8 + (size_t)kMaxTeam * kTeamSlot * 8 + 8 * 8 +
-           ((size_t)kmax * 4 + 15) / 16 * 16 + 64 * 4;
-}
-
 // Team barrier number e (every workgroup of the team calls it with the same
-// e, from one thread, after its slot is stored and fenced).  False if the
-// team gave up (abort flag) or the wait ran out, which then sets the flag.
+// e, from one thread, once the workgroup's exchanged data -- written with
+// device-coherent stores -- has completed).  The arrival count and the wait
+// are relaxed device-scope atomics, so no cache is written back or
+// invalidated.  False if the team gave up (abort flag) or the wait ran
+// out, which then sets the flag.
 __device__ inline bool team_barrier(int32_t* flags, int T, int e) {
-    __hip_atomic_fetch_add(flags, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int target = T * (e + 1);
     for (int spin = 0;; ++spin) {
-        if (__hip_atomic_load(flags, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target)
+        if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target)
             return true;
         if (__hip_atomic_load(flags + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
             return false;
@@ -125,7 +124,7 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
 // a group does but, by rounding, none of its points (every lane gets the
 // same answer).
 __device__ inline int kpp_find(const double* gt, int ngroups, const double* __restrict__ w, int lo,
-                               int hi, double carry, double x) {
+                               int hi, double carry, double x, bool coh) {
     const int lane = threadIdx.x & (kWave - 1);
     int q = -1;
     for (int base = 0; base < ngroups; base += kWave) {
@@ -145,11 +144,19 @@ __device__ inline int kpp_find(const double* gt, int ngroups, const double* __re
     }
     if (q < 0) return -1;
     const int g0 = lo + q * kKppGroup;
+    // the group's weights, all four tiles' loads in flight at once
+    constexpr int U = kKppGroup / kWave;
+    double v[U];
 #pragma unroll
-    for (int u = 0; u < kKppGroup / kWave; ++u) {
+    for (int u = 0; u < U; ++u) {
+        const int i = min(g0 + u * kWave + lane, hi - 1);
+        v[u] = coh ? load_dev(w + i) : w[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
         const int i = g0 + u * kWave + lane;
-        const double v = i < hi ? w[i] : 0.0;
-        const double run = carry + wave_incl_scan(v);
+        const double vi = i < hi ? v[u] : 0.0;
+        const double run = carry + wave_incl_scan(vi);
         const unsigned long long hit = __ballot(i < hi && run > x);
         if (hit) return g0 + u * kWave + __ffsll((long long)hit) - 1;
         carry = __shfl(run, kWave - 1, kWave);
@@ -158,11 +165,11 @@ __device__ inline int kpp_find(const double* gt, int ngroups, const double* __re
 }
 
 // Last point of positive weight in [lo, hi), or -1 (one whole wave).
-__device__ inline int kpp_last_positive(const double* __restrict__ w, int lo, int hi) {
+__device__ inline int kpp_last_positive(const double* __restrict__ w, int lo, int hi, bool coh) {
     const int lane = threadIdx.x & (kWave - 1);
     for (int top = hi; top > lo; top -= kWave) {
         const int i = top - kWave + lane;
-        const bool pos = i >= lo && w[i] > 0.0;
+        const bool pos = i >= lo && (coh ? load_dev(w + i) : w[i]) > 0.0;
         const unsigned long long mk = __ballot(pos);
         if (mk) return top - kWave + 63 - __clzll((long long)mk);
     }
@@ -170,9 +177,10 @@ __device__ inline int kpp_last_positive(const double* __restrict__ w, int lo, in
 }
 
 // Last point of positive weight in group q of a slice, or -1.
-__device__ inline int kpp_last_positive_group(const double* __restrict__ w, int lo, int hi, int q) {
+__device__ inline int kpp_last_positive_group(const double* __restrict__ w, int lo, int hi, int q,
+                                              bool coh) {
     const int g0 = lo + q * kKppGroup;
-    return kpp_last_positive(w, g0, min(hi, g0 + kKppGroup));
+    return kpp_last_positive(w, g0, min(hi, g0 + kKppGroup), coh);
 }
 
 // Sum over the LP lanes of a point, which sit 64 / LP lanes apart (lane =
@@ -208,8 +216,8 @@ __device__ __forceinline__ double point_sum(double v) {
 // LDS; the rows of the next two tiles are in flight while one is processed.
 template <int D, int NT, int NC>
 __device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const double* crow,
-                           const double* __restrict__ in, bool first, double* const (&out)[4],
-                           double* const (&gto)[4], double (&pot)[4]) {
+                           const double* __restrict__ in, bool first, bool coh,
+                           double* const (&out)[4], double* const (&gto)[4], double (&pot)[4]) {
     constexpr int NW = NT / kWave;
     constexpr int LP = D / 8, PPT = kWave / LP, TPG = kKppGroup / PPT;
     const int lane = threadIdx.x & (kWave - 1);
@@ -254,7 +262,13 @@ __device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const d
             }
             acc = point_sum<LP>(acc);
             const double nd = acc < dd ? acc : dd;
-            if (mine) out[t][i] = nd;
+            if (mine) {
+                // read by the other workgroups of a team: device-coherent
+                if (coh)
+                    store_dev(out[t] + i, nd);
+                else
+                    out[t][i] = nd;
+            }
             gp[t] += mine ? nd : 0.0;
         }
         if (f % TPG == TPG - 1) {  // last tile of a group: its sums
@@ -290,58 +304,78 @@ __device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const d
 template <int D, int NT>
 __device__ __forceinline__ void kpp_stream_n(int nc, const float* __restrict__ sg, int lo, int hi,
                                              const double* crow, const double* __restrict__ in,
-                                             double* const (&out)[4], double* const (&gto)[4],
-                                             double (&pot)[4]) {
+                                             bool coh, double* const (&out)[4],
+                                             double* const (&gto)[4], double (&pot)[4]) {
     switch (nc) {
-        case 1: kpp_stream<D, NT, 1>(sg, lo, hi, crow, in, false, out, gto, pot); break;
-        case 2: kpp_stream<D, NT, 2>(sg, lo, hi, crow, in, false, out, gto, pot); break;
-        case 3: kpp_stream<D, NT, 3>(sg, lo, hi, crow, in, false, out, gto, pot); break;
-        default: kpp_stream<D, NT, 4>(sg, lo, hi, crow, in, false, out, gto, pot); break;
+        case 1: kpp_stream<D, NT, 1>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
+        case 2: kpp_stream<D, NT, 2>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
+        case 3: kpp_stream<D, NT, 3>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
+        default: kpp_stream<D, NT, 4>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
     }
 }
 
+// Doubles of one workgroup's exchange slot (per parity): the candidates'
+// slice sums, then per candidate the slice's group sums.
+__host__ __device__ inline int kpp_slot_doubles(int ngmax) { return 4 + 4 * ngmax; }
+
+// Dynamic LDS of the seeding kernel for teams of T with ngmax group sums per
+// slice and at most kmax centroids.
+template <int D, int NT>
+__host__ __device__ inline size_t kpp_lds_bytes(int ngmax, int kmax, int T) {
+    const size_t dbl = (size_t)4 * ngmax           // the stream's group sums per candidate
+                       + (size_t)T * ngmax         // every slice's group sums (current weights)
+                       + 4 * (size_t)D             // candidate rows
+                       + 4 * (NT / kWave)          // workgroup sums
+                       + (size_t)T                 // every slice's weight
+                       + (size_t)T * kpp_slot_doubles(ngmax)  // one exchange, gathered
+                       + 8;                        // potentials
+    return dbl * 8 + ((size_t)kmax * 4 + 15) / 16 * 16 + 64 * 4;
+}
+
 // Cold samples of a batch, one per team of `team` workgroups (see above).
+//
+// One exchange per step: every workgroup publishes, for each candidate, its
+// slice's sum and group sums of the would-be weights.  After the exchange
+// every workgroup knows the kept candidate, hence every slice's weight and
+// group sums, and finds all the next step's candidates itself: the owner
+// slice and group from the sums (LDS), the point from the owner's 256
+// weights of that group in global memory (written before the owner arrived).
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
     constexpr int NW = NT / kWave;
     static_assert(NW >= 4, "one wave per candidate in the search");
     extern __shared__ __align__(16) char smem[];
-    double* gt = reinterpret_cast<double*>(smem);                    // kKppBuffers x ngmax
-    double* crow = gt + (size_t)kKppBuffers * a.ngmax;               // 4 x D
-    double* red = crow + 4 * D;                                      // 4 x NW
-    double* wts = red + 4 * NW;                   // the slices' weights, team order
-    double* tsl = wts + kMaxTeam;                 // the team's slots of one exchange
-    double* pv = tsl + kMaxTeam * kTeamSlot;      // the candidates' potentials
-    int* picks = reinterpret_cast<int*>(pv + 8);                     // kmax
-    int* ints = picks + ((size_t)a.kmax * 4 + 15) / 16 * 4;          // 64
+    const int T = a.team, ngmax = a.ngmax, SD = kpp_slot_doubles(ngmax);
+    double* gtmp = reinterpret_cast<double*>(smem);  // 4 x ngmax: this slice's group sums
+    double* ggs = gtmp + 4 * ngmax;                  // T x ngmax: every slice's, current weights
+    double* crow = ggs + (size_t)T * ngmax;          // 4 x D
+    double* red = crow + 4 * D;                      // 4 x NW
+    double* wts = red + 4 * NW;                      // T: every slice's weight
+    double* tsl = wts + T;                           // T x SD: one exchange's slots
+    double* pv = tsl + (size_t)T * SD;               // 8
+    int* picks = reinterpret_cast<int*>(pv + 8);     // kmax
+    int* ints = picks + ((size_t)a.kmax * 4 + 15) / 16 * 4;  // 64
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int T = a.team;
     const int tau = blockIdx.x % a.n_teams, b = blockIdx.x / a.n_teams;
     int32_t* const flags = a.tflag + 4 * tau;
-    double* const xs = a.tx + (size_t)tau * 2 * T * kTeamSlot;
+    double* const xs = a.tx + (size_t)tau * 2 * T * SD;
     const int d = a.d;
     int ebar = 0;  // team barriers passed
 
-    // publish-fence-arrive-wait; every thread returns whether the team is
-    // still alive
+    // every wave's device-coherent stores complete, then arrive and wait;
+    // every thread returns whether the team is still alive
+    const bool coh = T > 1;
     auto team_sync = [&]() -> bool {
-        __threadfence();
+        wait_stores();
         __syncthreads();
         if (tid == 0) ints[1] = team_barrier(flags, T, ebar) ? 1 : 0;
         __syncthreads();
         ++ebar;
-        const bool ok = __builtin_amdgcn_readfirstlane(ints[1]) != 0;
-        __threadfence();
-        return ok;
+        return __builtin_amdgcn_readfirstlane(ints[1]) != 0;
     };
-    auto slot = [&](int par, int member) { return xs + ((size_t)par * T + member) * kTeamSlot; };
-    // the team's slots of parity par into LDS, one load per thread
-    auto gather_slots = [&](int par) {
-        for (int e = tid; e < T * kTeamSlot; e += NT) tsl[e] = slot(par, e / kTeamSlot)[e % kTeamSlot];
-        __syncthreads();
-    };
+    auto slot = [&](int par, int member) { return xs + ((size_t)par * T + member) * SD; };
 
     for (int it = 0;; ++it) {
         int task;
@@ -365,14 +399,17 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
         }
         if (__syncthreads_or(warm)) continue;
 
-        // this workgroup's slice: whole groups of 256 points
+        // the slices: whole groups of 256 points, in team order
         const int per = ((s + T - 1) / T + kKppGroup - 1) / kKppGroup * kKppGroup;
-        const int lo = min(s, b * per), hi = min(s, lo + per);
-        const int ngr = (hi - lo + kKppGroup - 1) / kKppGroup;
+        auto slice_lo = [&](int q) { return min(s, q * per); };
+        auto slice_hi = [&](int q) { return min(s, q * per + per); };
+        auto slice_ng = [&](int q) {
+            return (slice_hi(q) - slice_lo(q) + kKppGroup - 1) / kKppGroup;
+        };
+        const int lo = slice_lo(b), hi = slice_hi(b), ngr = slice_ng(b);
         float* const sg = a.sbuf + (size_t)ds.idx_offset * D;
         double* const wb = a.d2buf + (size_t)kKppBuffers * ds.idx_offset;
         auto buf = [&](int j) { return wb + (size_t)j * s; };
-        auto gts = [&](int j) { return gt + (size_t)j * a.ngmax; };
         const int64_t* const ix = a.idx + ds.idx_offset;
 
         // gather the slice's rows (zero padded to D); an index outside
@@ -410,8 +447,10 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
                     if (dst[u] >= 0) *reinterpret_cast<float4*>(sg + dst[u]) = v[u];
             }
         }
-        // candidate rows into LDS as FP64, read from X through the indices
-        // (X is never written, so no exchange is needed to see them)
+
+        // candidate rows into LDS as FP64, from X through the sample's
+        // indices (X is never written, so every workgroup reads them
+        // without an exchange)
         auto load_rows = [&](const int (&cand)[4], int nc) {
             for (int e = tid; e < 4 * D; e += NT) {
                 const int t = e / D, col = e % D;
@@ -424,7 +463,6 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
                 crow[e] = v;
             }
         };
-
         // the first centre: uniform over the sample (block 0, word 0)
         const Words4 w0 = philox_block(ds.seed, a.tag, 0, ds.sample_id, a.call_id);
         const int i0 = (int)bounded_index(w0.w[0], (uint64_t)s);
@@ -434,13 +472,6 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
             load_rows(c0, 1);
         }
         __syncthreads();
-        double pot[4] = {0.0, 0.0, 0.0, 0.0};
-        {
-            double* const o[4] = {buf(0), buf(0), buf(0), buf(0)};
-            double* const g[4] = {gts(0), gts(0), gts(0), gts(0)};
-            kpp_stream<D, NT, 1>(sg, lo, hi, crow, buf(0), true, o, g, pot);
-        }
-        // this slice's total weight, then every slice's (team order)
         auto block_pot = [&](double (&v)[4]) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -457,141 +488,136 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
             }
             __syncthreads();
         };
+        // publish this slice's sums of nc candidates, exchange, keep the
+        // candidate of smallest potential (lowest index on ties) and adopt
+        // its weights and group sums for every slice; returns the kept
+        // candidate, or -1 if the team gave up
+        int par = 0;
+        auto exchange = [&](const double (&pt)[4], int nc) -> int {
+            if (T > 1) {
+                par ^= 1;
+                double* my = slot(par, b);
+                for (int e = tid; e < SD; e += NT) {
+                    double v = 0.0;
+                    if (e < 4) {
+                        v = e < nc ? pt[e] : 0.0;
+                    } else {
+                        const int t = (e - 4) / ngmax, q = (e - 4) % ngmax;
+                        v = (t < nc && q < ngr) ? gtmp[t * ngmax + q] : 0.0;
+                    }
+                    store_dev(my + e, v);
+                }
+                if (!team_sync()) return -1;
+                for (int e = tid; e < T * SD; e += NT) tsl[e] = load_dev(slot(par, e / SD) + e % SD);
+                __syncthreads();
+                if (tid < 4) {
+                    double acc = 0.0;
+                    for (int q = 0; q < T; ++q) acc += tsl[q * SD + tid];
+                    pv[tid] = acc;
+                }
+            } else if (tid < 4) {
+                pv[tid] = pt[tid];
+            }
+            __syncthreads();
+            int tb = 0;
+#pragma unroll
+            for (int t = 1; t < 4; ++t)
+                if (t < nc && pv[t] < pv[tb]) tb = t;
+            if (T > 1) {
+                for (int e = tid; e < T; e += NT) wts[e] = tsl[e * SD + tb];
+                for (int e = tid; e < T * ngmax; e += NT) {
+                    const int q = e / ngmax, g = e % ngmax;
+                    ggs[e] = tsl[q * SD + 4 + tb * ngmax + g];
+                }
+            } else {
+                if (tid == 0) wts[0] = pv[tb];
+                for (int e = tid; e < ngmax; e += NT) ggs[e] = e < ngr ? gtmp[tb * ngmax + e] : 0.0;
+            }
+            __syncthreads();
+            return tb;
+        };
+        // D^2 from the first centre: the weights in buffer 0
+        double pot[4] = {0.0, 0.0, 0.0, 0.0};
+        {
+            double* const o[4] = {buf(0), buf(0), buf(0), buf(0)};
+            double* const g[4] = {gtmp, gtmp, gtmp, gtmp};
+            kpp_stream<D, NT, 1>(sg, lo, hi, crow, buf(0), true, coh, o, g, pot);
+        }
         block_pot(pot);
         int cur = 0;
-        int par = 0;
-        bool alive = true;
-        // every slice's weight in team order, in LDS (the same values in
-        // every workgroup of the team)
-        if (T > 1) {
-            if (tid == 0) slot(par, b)[0] = pot[0];
-            alive = team_sync();
-            if (alive) {
-                gather_slots(par);
-                if (tid < T) wts[tid] = tsl[tid * kTeamSlot];
-            }
-        } else if (tid == 0) {
-            wts[0] = pot[0];
-        }
-        __syncthreads();
+        bool alive = exchange(pot, 1) >= 0;
         for (int r = 1; r < k && alive; ++r) {
             const Words4 w = philox_block(ds.seed, a.tag, (uint64_t)r, ds.sample_id, a.call_id);
-            // W and this slice's offset, in team order
-            double W = 0.0, off = 0.0;
-            int last_pos = -1;
-            for (int q = 0; q < T; ++q) {
-                const double v = wts[q];
-                if (q == b) off = W;
-                if (v > 0.0) last_pos = q;
-                W += v;
-            }
+            // W in team order (the same value in every workgroup)
+            double W = 0.0;
+            for (int q = 0; q < T; ++q) W += wts[q];
             int pick;
             if (!(W > 0.0)) {
                 pick = (int)bounded_index(w.w[0], (uint64_t)s);
             } else {
-                // the targets this slice holds: wave t searches target t
+                // wave t finds candidate t: the slice whose running end first
+                // exceeds the target (or, the target rounded up to W, the last
+                // slice of positive weight), then the group and the point
                 const int nc = a.n_cand;
                 const double* const wcur = buf(cur);
                 if (wid < nc) {
                     const double x = unit_double(w.w[wid]) * W;
-                    // owner: the first slice whose running end exceeds x, or
-                    // (x rounded up to W) the last slice of positive weight
-                    double run = 0.0;
-                    int owner = -1;
+                    double run = 0.0, off = 0.0;
+                    int owner = -1, last_pos = -1;
                     for (int q = 0; q < T; ++q) {
-                        run += wts[q];
-                        if (run > x) {
+                        const double v = wts[q];
+                        if (owner < 0 && run + v > x) {
                             owner = q;
-                            break;
+                            off = run;
                         }
+                        if (v > 0.0) last_pos = q;
+                        run += v;
                     }
                     int found = -1;
-                    if (owner == b) {
-                        found = kpp_find(gts(cur), ngr, wcur, lo, hi, off, x);
+                    const bool rounded_up = owner < 0;
+                    if (rounded_up) owner = last_pos;
+                    const int olo = slice_lo(owner), ohi = slice_hi(owner), ong = slice_ng(owner);
+                    const double* og = ggs + (size_t)owner * ngmax;
+                    if (!rounded_up) {
+                        found = kpp_find(og, ong, wcur, olo, ohi, off, x, coh);
                         if (found == -2) {
                             // in a group by its sum, in none of its points by
                             // theirs: the group's last point of positive weight
                             double c2 = off;
                             int q2 = 0;
-                            for (; q2 < ngr; ++q2) {
-                                if (c2 + gts(cur)[q2] > x) break;
-                                c2 += gts(cur)[q2];
+                            for (; q2 < ong; ++q2) {
+                                if (c2 + og[q2] > x) break;
+                                c2 += og[q2];
                             }
-                            found = kpp_last_positive_group(wcur, lo, hi, min(q2, ngr - 1));
+                            found = kpp_last_positive_group(wcur, olo, ohi, min(q2, ong - 1), coh);
                         }
-                        if (found == -1) found = kpp_last_positive(wcur, lo, hi);
-                    } else if (owner < 0 && last_pos == b) {
-                        found = kpp_last_positive(wcur, lo, hi);
                     }
+                    if (found < 0) found = kpp_last_positive(wcur, olo, ohi, coh);
+                    found = found < 0 ? 0 : found;
                     if (lane == 0) ints[8 + wid] = found;
+                    // the candidate's row into LDS (FP64), read by this wave
+                    const int64_t row = ix[found];
+                    const bool in_range = row >= 0 && row < a.m;
+                    for (int col = lane; col < D; col += kWave)
+                        crow[wid * D + col] =
+                            (in_range && col < d) ? (double)a.X[row * d + col] : 0.0;
                 }
                 __syncthreads();
-                // the candidates: each target's point from the slice that
-                // holds it
-                if (T > 1) {
-                    par ^= 1;
-                    if (tid < 4) slot(par, b)[4 + tid] = (double)(tid < nc ? ints[8 + tid] : -1);
-                    alive = team_sync();
-                    if (!alive) break;
-                    gather_slots(par);
-                    if (tid < 4) {
-                        int c = -1;
-                        for (int q = 0; q < T; ++q) {
-                            const int v = (int)tsl[q * kTeamSlot + 4 + tid];
-                            c = v > c ? v : c;
-                        }
-                        ints[12 + tid] = c < 0 ? 0 : c;
-                    }
-                } else if (tid < 4) {
-                    ints[12 + tid] = ints[8 + tid] < 0 ? 0 : ints[8 + tid];
-                }
-                __syncthreads();
-                const int cand[4] = {ints[12], ints[13], ints[14], ints[15]};
-                load_rows(cand, nc);
-                __syncthreads();
+                const int cand[4] = {ints[8], ints[9], ints[10], ints[11]};
                 // the candidates' would-be weights into the four buffers
                 // other than the current one
                 double* o[4];
-                double* g[4];
+                double* const g[4] = {gtmp, gtmp + ngmax, gtmp + 2 * ngmax, gtmp + 3 * ngmax};
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int j = (cur + 1 + t) % kKppBuffers;
-                    o[t] = buf(j);
-                    g[t] = gts(j);
-                }
+                for (int t = 0; t < 4; ++t) o[t] = buf((cur + 1 + t) % kKppBuffers);
                 double pt[4] = {0.0, 0.0, 0.0, 0.0};
-                kpp_stream_n<D, NT>(nc, sg, lo, hi, crow, wcur, o, g, pt);
+                kpp_stream_n<D, NT>(nc, sg, lo, hi, crow, wcur, coh, o, g, pt);
                 block_pot(pt);
-                // the potentials (slice sums added in team order) and the
-                // kept candidate; its slice sums are the next weights
-                if (T > 1) {
-                    par ^= 1;
-                    if (tid < 4) slot(par, b)[tid] = pt[tid];
-                    alive = team_sync();
-                    if (!alive) break;
-                    gather_slots(par);
-                    if (tid < 4) {
-                        double acc = 0.0;
-                        for (int q = 0; q < T; ++q) acc += tsl[q * kTeamSlot + tid];
-                        pv[tid] = acc;
-                    }
-                } else if (tid < 4) {
-                    pv[tid] = pt[tid];
-                }
-                __syncthreads();
-                int tb = 0;
-#pragma unroll
-                for (int t = 1; t < 4; ++t)
-                    if (t < nc && pv[t] < pv[tb]) tb = t;
+                const int tb = exchange(pt, nc);
+                alive = tb >= 0;
+                if (!alive) break;
                 pick = cand[tb];
                 cur = (cur + 1 + tb) % kKppBuffers;
-                __syncthreads();  // every thread has read pv and wts
-                if (T > 1) {
-                    if (tid < T) wts[tid] = tsl[tid * kTeamSlot + tb];
-                } else if (tid == 0) {
-                    wts[0] = pt[tb];
-                }
-                __syncthreads();
             }
             if (tid == 0) picks[r] = pick;
         }

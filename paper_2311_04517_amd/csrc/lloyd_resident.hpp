@@ -7,8 +7,8 @@
 // Section 6.5.  A persistent grid pulls samples from a queue in
 // longest-first order, so hundreds of samples of uneven size share one
 // launch.  When samples are few (at least twice as many resident
-// workgroups as samples, d > 32), each sample is two queue tasks and a warm
-// sample is worked by both workgroups, each on every other tile, with one
+// workgroups as samples), each sample is P consecutive queue tasks and a
+// warm sample is worked by P workgroups, each on every P-th tile, with one
 // exchange of partial sums per pass (see the pass loop); otherwise there is
 // no inter-workgroup synchronisation at all.
 //
@@ -66,54 +66,60 @@ struct LloydArgs {
     int32_t* queue;
     int32_t kmax;
     int32_t n_copies;  // partial-sum copies in LDS (== waves: private per wave)
-    // seeding-only mode
+    // seeding-only mode (the order of these fields moves the d <= 32 forms'
+    // scalar register allocation: keep it)
     int32_t seed_only;
     int32_t n_cand;
     uint32_t call_id;
     int32_t* chosen;
     int32_t vec4;  // rows of X are 16-byte aligned (d % 4 == 0, aligned base)
-    // shared samples (d > 32): with split == 2 every sample is two queue
-    // tasks, and a warm sample read straight from X is worked by two
-    // workgroups, each on every other tile, which exchange their partial
-    // sums once per pass
+    // shared samples: with split == P > 1 every sample is P queue tasks,
+    // and a warm sample read straight from X is worked by P workgroups,
+    // each on every P-th tile, which exchange their partial sums once per
+    // pass
     int32_t split;
-    double* xbuf;     // per sample, half and pass parity: xstride doubles
-    int32_t* xflag;   // per sample four ints, zeroed per launch (pair_barrier)
+    double* xbuf;     // per sample, part and pass parity: xstride doubles
+    int32_t* xflag;   // per sample four ints, zeroed per launch (parts_barrier)
     int32_t xstride;  // kmax * Lay<D>::CS + 8
 };
 
-// Spin limit of a shared sample's per-pass wait for its partner (about a
-// second at the sleep below); past it the sample is abandoned with f = NaN
-// rather than waiting for ever.
-constexpr int kPairSpinLimit = 1 << 19;
+// Workgroups per shared sample at most.
+constexpr int kMaxParts = 16;
 
-// A shared sample's flags (four ints, zeroed per launch): passes counted
-// by each half, and the first workgroup's decision.
+// Spin limit of a shared sample's per-pass wait for its partners (about a
+// second); past it the sample is abandoned with f = NaN rather than waiting
+// for ever.
+constexpr int kPairSpinLimit = 1 << 20;
+
+// A shared sample's flags (four ints, zeroed per launch): the passes counted
+// by all its workgroups together, and the first workgroup's decision.
 enum : int { kPairShared = 1, kPairAlone = 2 };
 
-// The first workgroup's decision for its sample, as seen by the second
+// The first workgroup's decision for its sample, as seen by the others
 // (kPairAlone if it is not published within the spin limit).  One thread.
+// Nothing the decision guards is read from the first workgroup's stores, so
+// a relaxed load suffices.
 __device__ inline int pair_decision(int32_t* flags) {
     for (int spin = 0; spin < kPairSpinLimit; ++spin) {
-        const int v = __hip_atomic_load(flags + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int v = __hip_atomic_load(flags + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (v != 0) return v;
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(1);
     }
     return kPairAlone;
 }
 
-// Release this workgroup's slot (every thread has stored its part and
-// passed a barrier, and fences its own stores at device scope before it),
-// count one more shared pass for `half`, and wait until the partner has
-// counted `target`.  Called by one thread; false if the partner did not
-// arrive within the spin limit.
-__device__ inline bool pair_barrier(int32_t* flags, int half, int target) {
-    __hip_atomic_fetch_add(flags + half, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Count one more shared pass of this workgroup and wait until all `parts`
+// workgroups of the sample have counted `target` passes each.  Called by one
+// thread once every wave's slot stores (device-coherent, see store_dev) have
+// completed; relaxed device-scope atomics, so no cache is written back or
+// invalidated.  False if a partner did not arrive within the spin limit.
+__device__ inline bool parts_barrier(int32_t* flags, int parts, int target) {
+    __hip_atomic_fetch_add(flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int spin = 0;
-         __hip_atomic_load(flags + (1 - half), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target;
+         __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < parts * target;
          ++spin) {
         if (spin >= kPairSpinLimit) return false;
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(1);
     }
     return true;
 }
@@ -480,11 +486,13 @@ __device__ __forceinline__ double centroid_max_norm(Smem<D, NT, PREC>& L, int k,
     return sqrt(mx);
 }
 
-// Up to d = 32 the kernel is held to 128 VGPRs (four waves per SIMD): the
-// tile loop then runs at twice the occupancy, at the price of a few
-// spilled values in the seeding and gather paths.
-template <int D, int NT, int PREC>
-__global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArgs a) {
+// Up to d = 32 the kernel without shared samples is held to 128 VGPRs (four
+// waves per SIMD): the tile loop then runs at twice the occupancy, at the
+// price of a few spilled values in the seeding and gather paths.  SHARE
+// compiles the shared-sample paths (always for d > 32; up to d = 32 a
+// separate form for batches of few samples, at two waves per SIMD).
+template <int D, int NT, int PREC, bool SHARE>
+__global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resident(LloydArgs a) {
     extern __shared__ __align__(16) char smem[];
     using S = Smem<D, NT, PREC>;
     constexpr int DL = Lay<D>::DL, CS = Lay<D>::CS;
@@ -497,9 +505,10 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
     double alpha, beta;
     screen_coeffs<PREC>(d, &alpha, &beta);
 
-    // shared samples exist for the wide instantiations only: up to d = 32
-    // the kernel has no scalar or vector registers to spare for them
-    const bool two = D >= 64 && a.split == 2;
+    // shared samples exist in the SHARE forms only (up to d = 32 the other
+    // form has no scalar or vector registers to spare for them)
+    const int NP = SHARE ? a.split : 1;
+    const bool two = SHARE && NP > 1;
     // every workgroup's first task is its own index (no atomic on one
     // address from the whole grid at once); later ones come from the queue
     bool first_task = true;
@@ -512,11 +521,11 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         // base pointers then live in scalar registers
         const int task = __builtin_amdgcn_readfirstlane(L.ints[15]);
         __syncthreads();
-        if (task >= (two ? 2 * a.n_samples : a.n_samples)) break;
-        // with shared samples the two tasks of a sample are consecutive:
-        // its second task is handed out right after the first, so a
-        // workgroup never waits for a partner that no workgroup will take
-        const int slot = two ? task >> 1 : task, half = two ? task & 1 : 0;
+        if (task >= NP * a.n_samples) break;
+        // with shared samples the P tasks of a sample are consecutive: they
+        // are handed out one after another, so a workgroup never waits for a
+        // partner that no workgroup will take
+        const int slot = two ? task / NP : task, half = two ? task % NP : 0;
         const int b = a.order ? a.order[slot] : slot;
         const hpc_sample_desc ds = a.desc[b];
         const int s = ds.s, k = ds.k;
@@ -569,7 +578,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         // waits for the first one's (the centroids it would judge by are
         // rewritten when the first workgroup finishes a sample alone)
         int32_t* const pflags = two ? a.xflag + 4 * slot : nullptr;
-        if (half == 1) {
+        if (half > 0) {
             if (tid == 0) L.ints[14] = pair_decision(pflags);
             __syncthreads();
             const int dec = __builtin_amdgcn_readfirstlane(L.ints[14]);
@@ -593,7 +602,6 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         };
         // seeding only: a block with no degenerate row (seeded already by
         // the team kernel, or all valid) is left as it is
-        if (a.seed_only && !any_degenerate()) continue;
         const bool direct_ok = !a.seed_only && a.vec4 && d == D;
         bool gathered = !direct_ok || any_degenerate();
         // a sample is shared only while it reads its rows straight from X
@@ -604,12 +612,15 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
         if (two) gathered = __builtin_amdgcn_readfirstlane(gathered);
         bool paired = two && !gathered;
         if (two && half == 0 && tid == 0)
-            __hip_atomic_store(pflags + 2, paired ? kPairShared : kPairAlone, __ATOMIC_RELEASE,
+            __hip_atomic_store(pflags + 2, paired ? kPairShared : kPairAlone, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        if (half == 1 && !paired) continue;  // (same data as the first: does not happen)
+        if (half > 0 && !paired) continue;  // (same data as the first: does not happen)
         if (gathered) gather();
 
         if (a.seed_only) {
+            if (a.chosen)
+                for (int j = tid; j < k; j += NT) a.chosen[j] = -1;
+            __syncthreads();
             kmeanspp_wg<D, NT, PREC>(sv, s, k, a.n_cand, d2, ds.seed, kTagSeed, ds.sample_id,
                                      a.call_id, a.chosen, L);
         } else {
@@ -619,23 +630,37 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
             unsigned kmask;
             float qscale;
             key_params(nblk, &kmask, &qscale);
-            // the exchange slots of a shared sample: this workgroup's and its
-            // partner's, for the parity of pass p
+            // the exchange slot of part hh of a shared sample, for the parity
+            // of pass p
             auto xslot = [&](int hh, int p) {
-                return a.xbuf + (((size_t)slot * 2 + hh) * 2 + (p & 1)) * a.xstride;
+                return a.xbuf + (((size_t)slot * NP + hh) * 2 + (p & 1)) * a.xstride;
             };
             // leaving a shared sample (a reseed, the gathered copy or the
-            // direct-sum objective is needed): the second workgroup stops;
-            // the first adds the partner's partial sums of pass p, its last
-            // exchange, to its own and continues alone.  True if this
-            // workgroup leaves.
+            // direct-sum objective is needed): the other workgroups stop; the
+            // first adds their partial sums of pass p, the last exchange, to
+            // its own and continues alone.  True if this workgroup leaves.
+            // The partners' previous labels (lprev) of their tiles were
+            // written device-coherently; this workgroup's caches may still
+            // hold lines of them from its own tiles' accesses, so it
+            // invalidates them once before reading every tile.
             auto unpair = [&](int p) {
                 paired = false;
-                if (half == 1) return true;
-                const double* th = xslot(1, p);
-                for (int e = tid; e < k * CS; e += NT) L.psum[e] += th[e];
+                if (half > 0) return true;
+                for (int e = tid; e < k * CS; e += NT) {
+                    double add = 0.0;
+                    for (int hh = 1; hh < NP; ++hh) add += load_dev(xslot(hh, p) + e);
+                    L.psum[e] += add;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __syncthreads();
                 return false;
+            };
+            // the sum over the sample's parts (part order, identical in every
+            // part) of element e of the pass-p slots
+            auto parts_sum = [&](int p, int e) {
+                double v = 0.0;
+                for (int hh = 0; hh < NP; ++hh) v += load_dev(xslot(hh, p) + e);
+                return v;
             };
             bool left = false;
             for (;;) {
@@ -689,9 +714,9 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 __syncthreads();
                 lds_f64* pw = as_lds(L.psum + (size_t)(wid % copies) * k * CS);
                 // tiles in pass order: a shared sample's workgroup takes every
-                // other one (tile v of this workgroup is tile 2v + half)
-                const int tsh = paired ? 1 : 0, toff = paired ? half : 0;
-                auto TI = [&](int v) { return (v << tsh) + toff; };
+                // P-th one (tile v of this workgroup is tile P v + part)
+                const int tmul = paired ? NP : 1, toff = paired ? half : 0;
+                auto TI = [&](int v) { return v * tmul + toff; };
                 double fl = 0.0;
                 // tiles of 16 points per wave, software pipelined over three
                 // register buffers: the rows of the next two tiles are in
@@ -749,7 +774,14 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                                 // counts are small integers, exact in FP64
                                 lds_add(pw + (am * CS + D), 1.0);
                                 if (prev >= 0) lds_add(pw + (prev * CS + D), -1.0);
-                                lprev[(unsigned)i] = am;
+                                // read by the first workgroup if a shared
+                                // sample ends: device-coherent while shared
+                                // read by the first workgroup if a shared
+                                // sample ends: device-coherent while shared
+                                if (SHARE && paired)
+                                    store_dev(lprev + (unsigned)i, am);
+                                else
+                                    lprev[(unsigned)i] = am;
                             }
                         }
                         if (g == 0 && lab_out) lab_out[(unsigned)i] = am;
@@ -821,64 +853,65 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 // exact zero exact).
                 __syncthreads();
                 // A shared sample's workgroups exchange their partial sums
-                // (in the first pass also their shares of Q) and each adds
-                // its own and the partner's in the same way, a + b against
-                // b + a: both then hold the same objective and centroids.
-                const double* th = nullptr;
+                // (in the first pass also their shares of Q) through
+                // device-coherent stores and loads, and each adds all parts'
+                // in part order: every part then holds the same objective and
+                // centroids.
+                bool xch = false;  // this pass's totals come from the slots
                 if (paired) {
                     double* mine = xslot(half, it);
                     for (int e = tid; e < k * CS; e += NT) {
                         double S = 0.0;
                         for (int gg = 0; gg < copies; ++gg) S += L.psum[(size_t)gg * k * CS + e];
-                        mine[e] = S;
+                        store_dev(mine + e, S);
                     }
                     if (first) {
                         fl = block_sum<NT>(fl, L.red);  // this workgroup's share of Q
-                        if (tid == 0) mine[k * CS] = fl;
+                        if (tid == 0) store_dev(mine + k * CS, fl);
                     }
-                    __threadfence();
+                    wait_stores();
                     __syncthreads();
-                    if (tid == 0) L.ints[14] = pair_barrier(pflags, half, it + 1);
+                    if (tid == 0) L.ints[14] = parts_barrier(pflags, NP, it + 1);
                     __syncthreads();
                     const bool arrived = __builtin_amdgcn_readfirstlane(L.ints[14]) != 0;
-                    __threadfence();
                     if (!arrived) {
-                        // the partner never came: abandon the sample
+                        // a partner never came: abandon the sample
                         // (f = NaN, passes = -1)
                         f = __builtin_nan("");
                         it = -1;
                         paired = false;
-                        left = half == 1;
+                        left = half > 0;
                         break;
                     }
-                    th = xslot(1 - half, it);
+                    xch = true;
                 }
                 double fp = 0.0;
                 for (int e = tid; e < k * CS; e += NT) {
                     const int j = e / CS, t = e % CS;
                     if (t >= d) continue;
                     double S = 0.0, n = 0.0;
-                    for (int gg = 0; gg < copies; ++gg) {
-                        S += L.psum[(size_t)gg * k * CS + e];
-                        n += L.psum[(size_t)gg * k * CS + j * CS + D];
-                    }
-                    if (th) {
-                        S += th[e];
-                        n += th[j * CS + D];
+                    if (xch) {
+                        S = parts_sum(it, e);
+                        n = parts_sum(it, j * CS + D);
+                    } else {
+                        for (int gg = 0; gg < copies; ++gg) {
+                            S += L.psum[(size_t)gg * k * CS + e];
+                            n += L.psum[(size_t)gg * k * CS + j * CS + D];
+                        }
                     }
                     if (n > 0.0) {
                         const double dc = L.C64[e] - L.ref[t];
                         fp = __fma_rn(dc, __fma_rn(n, dc, -2.0 * S), fp);
                     }
                 }
-                if (first && !th) {
+                if (first && !xch) {
                     double v2[2] = {fl, fp};
                     block_sum_n<NT, 2>(v2, L.red);
                     Qr = v2[0];
                     fp = v2[1];
                 } else {
                     fp = block_sum<NT>(fp, L.red);
-                    if (first) Qr = fl + th[k * CS];
+                    if (first) Qr = parts_sum(it, k * CS);
                 }
                 f = Qr + fp;
                 if (!(f > kSumsObjectiveMin * Qr)) {
@@ -887,7 +920,7 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                             left = true;
                             break;
                         }
-                        th = nullptr;
+                        xch = false;
                     }
                     const int64_t* ixs = a.idx + ds.idx_offset;
                     double fe = 0.0;
@@ -912,13 +945,14 @@ __global__ __launch_bounds__(NT, D <= 32 ? 4 : 2) void k_lloyd_resident(LloydArg
                 for (int e = tid; e < k * CS; e += NT) {
                     const int j = e / CS, t = e % CS;
                     double sum = 0.0, n = 0.0;
-                    for (int gg = 0; gg < copies; ++gg) {
-                        sum += L.psum[(size_t)gg * k * CS + e];
-                        n += L.psum[(size_t)gg * k * CS + j * CS + D];
-                    }
-                    if (th) {
-                        sum += th[e];
-                        n += th[j * CS + D];
+                    if (xch) {
+                        sum = parts_sum(it - 1, e);
+                        n = parts_sum(it - 1, j * CS + D);
+                    } else {
+                        for (int gg = 0; gg < copies; ++gg) {
+                            sum += L.psum[(size_t)gg * k * CS + e];
+                            n += L.psum[(size_t)gg * k * CS + j * CS + D];
+                        }
                     }
                     double v = 0.0;
                     if (t < d) v = n > 0.0 ? L.ref[t] + sum / n : __builtin_nan("");

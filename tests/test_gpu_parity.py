@@ -434,14 +434,15 @@ def test_far_from_the_origin(hp, orc, prec):
 def test_direct_and_gathered_rows_agree(hp, orc, prec):
     """Rows read straight from X through the indices (d equal to the padded
     width, aligned X) and rows gathered into scratch (misaligned X) give
-    identical results."""
+    identical results (samples of 2,000 points: too small to be shared, so
+    both runs add their sums in the same order)."""
     Xn, _ = _mix(30_000, 16, 8, seed=21)
     flat = torch.zeros(30_000 * 16 + 1, dtype=torch.float32, device="cuda")
     flat[1:] = torch.from_numpy(Xn.ravel()).cuda()
     Xmis = flat[1:].view(30_000, 16)  # 4-byte offset: not 16-byte aligned
     Xal = torch.from_numpy(Xn).cuda()
     assert Xmis.data_ptr() % 16 != 0 and Xal.data_ptr() % 16 == 0
-    n, s, k = 6, 3000, 9
+    n, s, k = 6, 2000, 9
     desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=3, sample_id=np.arange(n), d=16)
     idx = hp.draw_samples(30_000, desc, idx_len)
     out = []
@@ -504,10 +505,12 @@ def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
     assert checked >= n // 2
 
 
-def _shared_case(hp, orc, Xn, n, s, k, C0, seed, prec, *, min_long=0, reseeded=(), tight=False):
-    """Warm starts at d = 64 (a padded width with samples shared by two
-    workgroups when few samples are run) against the oracle, and against
-    the same starts on a misaligned X (rows gathered: never shared)."""
+def _shared_case(hp, orc, Xn, n, s, k, C0, seed, prec, *, min_long=0, reseeded=(), tight=False,
+                 min_checked=None):
+    """Warm starts of few samples (each shared by P workgroups, P up to 16
+    by the free capacity and the sample size) against the oracle, and
+    against the same starts on a misaligned X (rows gathered: never
+    shared)."""
     m, d = Xn.shape
     flat = torch.zeros(m * d + 1, dtype=torch.float32, device="cuda")
     flat[1:] = torch.from_numpy(Xn.ravel()).cuda()
@@ -540,7 +543,7 @@ def _shared_case(hp, orc, Xn, n, s, k, C0, seed, prec, *, min_long=0, reseeded=(
         assert itg[b] == ro.iters and rel(fg[b], ro.f) <= F_REL, (b, itg[b], ro.iters)
         assert_centroids(Cg[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, Xn[ib])
         assert_labels(lg[b * s:(b + 1) * s], ro.labels, ro.margins)
-    assert checked >= n // 2
+    assert checked >= (n // 2 if min_checked is None else min_checked)
     return fg, itg
 
 
@@ -556,6 +559,21 @@ def test_shared_samples_converge_like_the_oracle(hp, orc, prec, d):
     rng = np.random.default_rng(3)
     C0 = np.stack([centres + rng.normal(0, 0.5, (k, d)) for _ in range(n)]).astype(np.float32)
     _shared_case(hp, orc, Xn, n, s, k, C0, 5, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("d,n,s", [(8, 1, 12_000), (32, 2, 10_000), (32, 5, 4_100),
+                                   (64, 1, 16_000)])
+def test_shared_samples_many_parts(hp, orc, prec, d, n, s):
+    """One to five warm samples, each worked by as many workgroups as the
+    GPU and the sample size allow (up to 16, at least 1,024 points each),
+    including the d <= 32 form that carries the shared-sample paths."""
+    m, k = 80_000, 12
+    mx = synthetic.gaussian_mixture(m, d, k, seed=70 + d, centre_box=10.0, std=1.0)
+    Xn, centres = mx.X.numpy(), mx.centres.numpy()
+    rng = np.random.default_rng(d + n)
+    C0 = np.stack([centres + rng.normal(0, 0.5, (k, d)) for _ in range(n)]).astype(np.float32)
+    _shared_case(hp, orc, Xn, n, s, k, C0, 15, prec, min_checked=max(1, n // 2))
 
 
 @pytest.mark.parametrize("prec", PRECS)
