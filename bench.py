@@ -317,8 +317,10 @@ def run_metric(api, X, args, prec):
     stream = torch.cuda.current_stream()
 
     # one plan for every round: descriptors uploaded once, sample ids
-    # advanced on the device; its launch configuration is autotuned (warm
-    # passes on a throwaway round) before anything is timed
+    # advanced on the device; its launch configuration is autotuned on a
+    # throwaway warm round (centroids converged on one draw, Lloyd to the
+    # stop rule on the next draw, as every timed round runs) before anything
+    # is timed, and the sample ids are then reset
     desc, idx_len, c_len = api.make_desc([s] * W, [k] * W, seed=args.seed, sample_id=range(W), d=d)
     plan = api.Plan(d, desc, idx_len, c_len, precision=prec)
     tune = {}
@@ -327,9 +329,12 @@ def run_metric(api, X, args, prec):
 
         plan.draw(m, idx)
         Ct = torch.full((c_len,), float("nan"), device=dev)
-        plan.lloyd(X, idx, Ct)  # converged start, so the timed passes are warm ones
-        tune, ms = tuning.tuned(plan, X, idx, Ct, max_iter=3, retune=True)
-        print(f"[bench] precision {prec}: autotuned {tune} ({ms:.3f} ms for 3 passes)",
+        plan.lloyd(X, idx, Ct)
+        plan.advance(W)
+        plan.draw(m, idx)
+        tune, ms = tuning.tuned(plan, X, idx, Ct, max_iter=300, rel_tol=1e-4, retune=True)
+        plan.reset_ids()
+        print(f"[bench] precision {prec}: autotuned {tune} ({ms:.3f} ms for a warm round)",
               file=sys.stderr, flush=True)
         del Ct
 
@@ -578,9 +583,9 @@ def pmc_target(api, X, m, d, W, s, k, prec, seed):
     plan.draw(m, idx)
     C = torch.full((c_len,), float("nan"), device=X.device)
     plan.lloyd(X, idx, C)
-    tuning.tuned(plan, X, idx, C, max_iter=3, retune=True)
     plan.advance(W)
     plan.draw(m, idx)
+    tuning.tuned(plan, X, idx, C, max_iter=300, rel_tol=1e-4, retune=True)
     torch.cuda.synchronize()
     print("[bench] pmc target: warm batch next", file=sys.stderr, flush=True)
     plan.lloyd(X, idx, C, max_iter=3, rel_tol=0.0)

@@ -290,6 +290,14 @@ typedef struct {
     int32_t seed_inflight; /* cold samples seeded at once at most (0 = as many
                           teams as are resident; fewer keep the samples'
                           rows and weights in the last-level cache)        */
+    int32_t parts;     /* workgroups per warm sample, 0..16 (at most one per
+                          1024 points of the smallest sample); 0 = automatic:
+                          shared only when at least twice as many
+                          workgroups are resident as there are samples.  A
+                          value above resident/samples runs the samples in
+                          turn, each on `parts` workgroups, which shortens
+                          the tail of a batch whose samples need uneven
+                          numbers of passes                                */
 } hpc_tune;
 
 /* Create a plan on the current device for n_samples samples (desc: HOST
@@ -297,9 +305,10 @@ typedef struct {
  * 1 <= n_samples <= 65535) of d-dimensional data, screening precision
  * `precision`.  The plan owns its device memory (about idx_len * (4*pad(d)
  * + 44) bytes, pad(d) the next of 8, 16, 32, 64, 128, plus, where samples
- * can be shared (hpc_lloyd_batch), n_samples * 32 * (kmax * (pad(d) + 1) +
- * 8) bytes of exchange slots) until hpc_plan_destroy.  *out receives the handle (NULL on error).  The default
- * configuration is {0, 0, 0, 0}. */
+ * can be shared (the smallest sample has s_min >= 2048 points),
+ * n_samples * 16 * (P + 1) * (kmax * (pad(d) + 1) + 8) bytes of exchange
+ * slots, P = min(16, s_min / 1024)) until hpc_plan_destroy.  *out receives the
+ * handle (NULL on error).  The default configuration is all zeros. */
 int hpc_plan_create(int32_t d, const hpc_sample_desc *desc, int32_t n_samples, int64_t idx_len,
                     int64_t c_len, int32_t precision, hpc_plan *out);
 
@@ -308,10 +317,10 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc *desc, int32_t n_samples, i
 int hpc_plan_destroy(hpc_plan plan);
 
 /* Set / read the launch configuration.  Errors: wg_per_cu < 0, copies
- * outside [0, 4], order outside {0, 1}, seed_team outside [0, 64], seed_inflight < 0,
- * or a configuration
- * whose LDS does not fit.  A captured round keeps the configuration it was
- * captured with. */
+ * outside [0, 4], order outside {0, 1}, seed_team outside [0, 64],
+ * seed_inflight < 0, parts outside [0, 16], or a configuration whose LDS
+ * does not fit.  A parts value above the plan's limit is clamped to it.  A
+ * captured round keeps the configuration it was captured with. */
 int hpc_plan_set_tune(hpc_plan plan, const hpc_tune *tune);
 int hpc_plan_get_tune(hpc_plan plan, hpc_tune *tune);
 
@@ -320,16 +329,20 @@ int hpc_plan_get_tune(hpc_plan plan, hpc_tune *tune);
  * mean s), NUL-terminated into buf (host, len bytes). */
 int hpc_plan_tune_key(hpc_plan plan, char *buf, int32_t len);
 
-/* Autotuner: times every configuration (copies in {1, 2, 4} x wg_per_cu
- * from 1 to the occupancy limit x both orders when the samples are uneven)
- * on the caller's inputs -- hpc_plan_lloyd from a copy of C, max_iter
- * passes, no early stop -- keeps the fastest (HIP-event time, best of two)
- * as the plan's configuration and returns it in *best (host) and its time
- * in *best_ms (host, nullable).  C is not modified.  SYNCHRONOUS: returns
- * after the timing runs on hip_stream have finished. */
+/* Autotuner: times every configuration (parts per sample automatic and
+ * each power of two up to the plan's limit x copies in {1, 2, 4} x
+ * wg_per_cu from 1 to the occupancy limit of that kernel form x both
+ * orders when the samples are uneven; seeding knobs stay 0) on the
+ * caller's inputs -- hpc_plan_lloyd from a copy of C with max_iter and
+ * rel_tol (0 = exactly max_iter passes; the caller's stop rule times the
+ * tail of samples that need more passes than others) -- keeps the fastest
+ * (HIP-event time, best of two) as the plan's configuration and returns it
+ * in *best (host) and its time in *best_ms (host, nullable).  C is not
+ * modified.  SYNCHRONOUS: returns after the timing runs on hip_stream have
+ * finished. */
 int hpc_plan_autotune(hpc_plan plan, const float *X, int64_t m, const int64_t *idx,
-                      const float *C, int32_t max_iter, hpc_tune *best, double *best_ms,
-                      void *hip_stream);
+                      const float *C, int32_t max_iter, double rel_tol, hpc_tune *best,
+                      double *best_ms, void *hip_stream);
 
 /* hpc_lloyd_batch on the plan's samples (same arithmetic, outputs and
  * errors).  idx holds idx_len indices and C c_len floats, as at creation.

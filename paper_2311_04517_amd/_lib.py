@@ -46,11 +46,13 @@ class Tune(ct.Structure):
         ("order", ct.c_int32),
         ("seed_team", ct.c_int32),
         ("seed_inflight", ct.c_int32),
+        ("parts", ct.c_int32),
     ]
 
     def as_dict(self):
         return {"wg_per_cu": self.wg_per_cu, "copies": self.copies, "order": self.order,
-                "seed_team": self.seed_team, "seed_inflight": self.seed_inflight}
+                "seed_team": self.seed_team, "seed_inflight": self.seed_inflight,
+                "parts": self.parts}
 
 
 class HpcError(RuntimeError):
@@ -84,7 +86,7 @@ _SIGS = {
     "hpc_plan_set_tune": ([_p, _p], ct.c_int),
     "hpc_plan_get_tune": ([_p, _p], ct.c_int),
     "hpc_plan_tune_key": ([_p, ct.c_char_p, _i32], ct.c_int),
-    "hpc_plan_autotune": ([_p, _p, _i64, _p, _p, _i32, _p, _p, _p], ct.c_int),
+    "hpc_plan_autotune": ([_p, _p, _i64, _p, _p, _i32, _f64, _p, _p, _p], ct.c_int),
     "hpc_plan_lloyd": ([_p, _p, _i64, _p, _p, _i32, _f64, _p, _p, _p, _p], ct.c_int),
     "hpc_plan_draw": ([_p, _i64, _p, _p], ct.c_int),
     "hpc_plan_advance": ([_p, _u64, _p], ct.c_int),

@@ -208,8 +208,8 @@ class Plan:
         check(lib().hpc_plan_get_tune(self._h, ct.byref(t)), "hpc_plan_get_tune")
         return t
 
-    def set_tune(self, wg_per_cu=0, copies=0, order=0, seed_team=0, seed_inflight=0):
-        t = Tune(wg_per_cu, copies, order, seed_team, seed_inflight)
+    def set_tune(self, wg_per_cu=0, copies=0, order=0, seed_team=0, seed_inflight=0, parts=0):
+        t = Tune(wg_per_cu, copies, order, seed_team, seed_inflight, parts)
         check(lib().hpc_plan_set_tune(self._h, ct.byref(t)), "hpc_plan_set_tune")
 
     def tune_key(self) -> str:
@@ -217,16 +217,17 @@ class Plan:
         check(lib().hpc_plan_tune_key(self._h, buf, 256), "hpc_plan_tune_key")
         return buf.value.decode()
 
-    def autotune(self, X, idx, C, *, max_iter=3):
-        """Time every launch configuration on these inputs and keep the
-        fastest (synchronous).  Returns (Tune, ms)."""
+    def autotune(self, X, idx, C, *, max_iter=3, rel_tol=0.0):
+        """Time every launch configuration on these inputs (Lloyd from C,
+        max_iter passes, stop rule rel_tol; 0 = exactly max_iter) and keep
+        the fastest (synchronous).  Returns (Tune, ms)."""
         _dev(X, torch.float32, "X")
         _dev(idx, torch.int64, "idx")
         _dev(C, torch.float32, "C")
         t = Tune()
         ms = ct.c_double()
         check(lib().hpc_plan_autotune(self._h, _ptr(X), X.shape[0], _ptr(idx), _ptr(C), max_iter,
-                                      ct.byref(t), ct.byref(ms), ct.c_void_p(_stream())),
+                                      rel_tol, ct.byref(t), ct.byref(ms), ct.c_void_p(_stream())),
               "hpc_plan_autotune")
         return t, ms.value
 

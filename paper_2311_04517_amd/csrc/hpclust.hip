@@ -215,10 +215,10 @@ struct ResGeo {
 };
 
 // Doubles of the exchange buffer for n samples of `parts` workgroups: per
-// part two pass parities, and per slot the partial sums (kmax rows of D + 1)
-// and Q.
+// part and for the totals two pass parities, and per slot the partial sums
+// (kmax rows of D + 1), Q and the part's share of the objective.
 size_t xbuf_doubles(int n, int parts, int kmax, int D) {
-    return (size_t)n * parts * 2 * ((size_t)kmax * (D + 1) + 8);
+    return (size_t)n * (parts + 1) * 2 * ((size_t)kmax * (D + 1) + 8);
 }
 
 // Points a part of a shared sample keeps at least (eight tiles per wave).
@@ -231,16 +231,25 @@ constexpr bool share_form(bool shared) {
     return D >= 64 ? true : shared;
 }
 
+// Parts per sample a batch can use at most (s_min points in its smallest
+// sample).
+int parts_limit(int s_min) {
+    return std::max(1, std::min(hpc::kMaxParts, s_min / kMinPartPoints));
+}
+
 // Launch geometry for a batch of n_wg samples (at most kmax centroids, the
 // smallest s_min points).  copies_req 0 = as many private copies as fit in
 // 64 KiB; wg_per_cu 0 = as many workgroups per CU as the occupancy allows.
-// With max_parts > 1 and at least twice as many resident workgroups (of the
-// shared form) as samples, every sample gets P = min(resident / samples,
-// max_parts, s_min / kMinPartPoints) workgroups (warm samples are then
-// shared).
+// parts_req 0: with max_parts > 1 and at least twice as many resident
+// workgroups (of the shared form) as samples, every sample gets P =
+// min(resident / samples, max_parts, parts_limit) workgroups (warm samples
+// are then shared).  parts_req > 0 asks for P = min(parts_req, max_parts,
+// parts_limit, resident) whatever the number of samples: samples beyond
+// the resident grid then wait in the queue, and the grid is a whole number
+// of samples' parts.
 template <int D, int PREC>
 int resident_geometry(int kmax, int n_wg, int s_min, int wg_per_cu, int copies_req,
-                      int max_parts, ResGeo* out) {
+                      int max_parts, int parts_req, ResGeo* out) {
     using S = hpc::Smem<D, kNT, PREC>;
     constexpr int NW = kNT / hpc::kWave;
     int lds_max = 0;
@@ -280,10 +289,10 @@ int resident_geometry(int kmax, int n_wg, int s_min, int wg_per_cu, int copies_r
     if (rc) return rc;
     int parts = 1;
     if (max_parts > 1) {
-        const int64_t by_size = std::max(1, s_min / kMinPartPoints);
+        const int64_t lim = std::min(max_parts, parts_limit(s_min));
         parts = (int)std::max<int64_t>(
-            1, std::min<int64_t>({cap_s / n_wg, (int64_t)max_parts, (int64_t)hpc::kMaxParts,
-                                  by_size}));
+            1, parts_req > 0 ? std::min<int64_t>({(int64_t)parts_req, lim, cap_s})
+                             : std::min<int64_t>(cap_s / n_wg, lim));
     }
     int per_cu = per_s;
     int64_t cap = cap_s;
@@ -294,7 +303,7 @@ int resident_geometry(int kmax, int n_wg, int s_min, int wg_per_cu, int copies_r
     }
     out->split = parts;
     out->share = share;
-    out->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)n_wg * parts, cap));
+    out->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)n_wg * parts, cap / parts * parts));
     out->copies = copies;
     out->lds = lds;
     out->per_cu_max = per_cu;
@@ -326,7 +335,7 @@ int launch_resident(hpc::LloydArgs a, const ResGeo& g, hipStream_t st) {
 int resident_geo(int D, int prec, int kmax, int n_wg, int s_min, int max_parts, ResGeo* g) {
     return with_dp(D, prec, [&](auto Dc, auto Pc) {
         return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(kmax, n_wg, s_min, 0, 0,
-                                                                           max_parts, g);
+                                                                           max_parts, 0, g);
     });
 }
 
@@ -781,7 +790,7 @@ int plan_check(hpc_plan p, const char* where) {
 int plan_geometry(hpc_plan p, const hpc_tune& t, ResGeo* g, int max_parts) {
     return with_dp(p->D, p->prec, [&](auto Dc, auto Pc) {
         return resident_geometry<decltype(Dc)::value, decltype(Pc)::value>(
-            p->kmax, p->n, p->smin, t.wg_per_cu, t.copies, max_parts, g);
+            p->kmax, p->n, p->smin, t.wg_per_cu, t.copies, max_parts, t.parts, g);
     });
 }
 
@@ -1162,16 +1171,12 @@ int hpc_plan_create(int32_t d, const hpc_sample_desc* desc, int32_t n_samples, i
     };
     if (hipGetDevice(&p->device) != hipSuccess)
         return cleanup(fail(HPC_ERR_HIP, "hpc_plan_create: hipGetDevice failed"));
-    // samples can be shared only if the default geometry (the most
-    // workgroups per CU) shares them; then the exchange buffers are made for
-    // its parts per sample, the most any configuration of this plan uses
+    // the exchange buffers serve the most parts per sample any configuration
+    // of this plan can ask for (set by the smallest sample)
     p->smin = INT32_MAX;
     for (int32_t b = 0; b < n_samples; ++b) p->smin = std::min(p->smin, desc[b].s);
-    ResGeo g0;
-    rc = plan_geometry(p, p->tune, &g0, hpc::kMaxParts);
-    if (rc) return cleanup(rc);
-    const bool shareable = g0.split > 1;
-    p->xparts = g0.split;
+    p->xparts = parts_limit(p->smin);
+    const bool shareable = p->xparts > 1;
     const size_t desc_b = (size_t)n_samples * sizeof(hpc_sample_desc);
     const size_t order_b = (size_t)n_samples * 8;
     const size_t sbuf_b = (size_t)idx_len * p->D * 4;
@@ -1266,11 +1271,11 @@ int hpc_plan_set_tune(hpc_plan plan, const hpc_tune* tune) {
     if (rc) return rc;
     if (!tune || tune->wg_per_cu < 0 || tune->copies < 0 || tune->copies > 4 || tune->order < 0 ||
         tune->order > 1 || tune->seed_team < 0 || tune->seed_team > kKppMaxTeam ||
-        tune->seed_inflight < 0)
+        tune->seed_inflight < 0 || tune->parts < 0 || tune->parts > hpc::kMaxParts)
         return fail(HPC_ERR_INVALID_ARG,
                     "hpc_plan_set_tune: need wg_per_cu>=0, copies in [0,4], order in {0,1}, "
-                    "seed_team in [0,%d], seed_inflight>=0",
-                    kKppMaxTeam);
+                    "seed_team in [0,%d], seed_inflight>=0, parts in [0,%d]",
+                    kKppMaxTeam, hpc::kMaxParts);
     ResGeo g;
     rc = plan_geometry(plan, *tune, &g);
     if (rc) return rc;
@@ -1303,25 +1308,32 @@ int hpc_plan_tune_key(hpc_plan plan, char* buf, int32_t len) {
 }
 
 int hpc_plan_autotune(hpc_plan plan, const float* X, int64_t m, const int64_t* idx,
-                      const float* C, int32_t max_iter, hpc_tune* best, double* best_ms,
-                      void* hip_stream) {
+                      const float* C, int32_t max_iter, double rel_tol, hpc_tune* best,
+                      double* best_ms, void* hip_stream) {
     int rc = plan_check(plan, "hpc_plan_autotune");
     if (rc) return rc;
-    rc = lloyd_opts_ok("hpc_plan_autotune", X, m, idx, C, max_iter, 0.0, plan->tf, plan->tit);
+    rc = lloyd_opts_ok("hpc_plan_autotune", X, m, idx, C, max_iter, rel_tol, plan->tf, plan->tit);
     if (rc) return rc;
     if (!best) return fail(HPC_ERR_INVALID_ARG, "hpc_plan_autotune: NULL best");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     bool uneven = false;
     for (const auto& ds : plan->desc)
         uneven |= (int64_t)ds.s * ds.k != (int64_t)plan->desc[0].s * plan->desc[0].k;
+    // parts per sample: automatic, then every power of two the plan's
+    // exchange buffers serve (each a distinct geometry)
+    std::vector<int> parts_opts{0};
+    for (int P = 1; P <= plan->xparts; P *= 2) parts_opts.push_back(P);
     std::vector<hpc_tune> cand;
-    for (int copies : {1, 2, 4}) {
-        hpc_tune t{0, copies, 0, 0};
-        ResGeo g;
-        if (plan_geometry(plan, t, &g) != HPC_OK) continue;  // does not fit: skip
-        for (int w = 1; w <= g.per_cu_max; ++w)
-            for (int o = 0; o <= (uneven ? 1 : 0); ++o) cand.push_back(hpc_tune{w, copies, o, 0, 0});
-    }
+    for (int P : parts_opts)
+        for (int copies : {1, 2, 4}) {
+            hpc_tune t{0, copies, 0, 0, 0, P};
+            ResGeo g;
+            if (plan_geometry(plan, t, &g) != HPC_OK) continue;  // does not fit: skip
+            if (P > 0 && g.split != P) continue;                 // not a geometry of its own
+            for (int w = 1; w <= g.per_cu_max; ++w)
+                for (int o = 0; o <= (uneven ? 1 : 0); ++o)
+                    cand.push_back(hpc_tune{w, copies, o, 0, 0, P});
+        }
     if (cand.empty()) return fail(HPC_ERR_UNSUPPORTED, "hpc_plan_autotune: no configuration fits");
     hipEvent_t e0, e1;
     HPC_HIP(hipEventCreate(&e0));
@@ -1331,7 +1343,7 @@ int hpc_plan_autotune(hpc_plan plan, const float* X, int64_t m, const int64_t* i
         int r = plan_geometry(plan, t, &g);
         if (r) return r;
         HPC_HIP(hipMemcpyAsync(plan->tC, C, (size_t)plan->c_len * 4, hipMemcpyDeviceToDevice, st));
-        const hpc::LloydArgs a = plan_args(plan, X, m, idx, plan->tC, max_iter, 0.0, plan->tf,
+        const hpc::LloydArgs a = plan_args(plan, X, m, idx, plan->tC, max_iter, rel_tol, plan->tf,
                                            plan->tit, nullptr, t.order);
         HPC_HIP(hipEventRecord(e0, st));
         r = plan_launch(plan, a, g, st);

@@ -631,9 +631,9 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
             float qscale;
             key_params(nblk, &kmask, &qscale);
             // the exchange slot of part hh of a shared sample, for the parity
-            // of pass p
+            // of pass p; slot NP holds the totals over the parts
             auto xslot = [&](int hh, int p) {
-                return a.xbuf + (((size_t)slot * NP + hh) * 2 + (p & 1)) * a.xstride;
+                return a.xbuf + (((size_t)slot * (NP + 1) + hh) * 2 + (p & 1)) * a.xstride;
             };
             // leaving a shared sample (a reseed, the gathered copy or the
             // direct-sum objective is needed): the other workgroups stop; the
@@ -643,24 +643,27 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
             // written device-coherently; this workgroup's caches may still
             // hold lines of them from its own tiles' accesses, so it
             // invalidates them once before reading every tile.
+            // the sum over parts [h0, NP) of the sample (part order, identical
+            // in every part) of element e of the pass-p slots; every load is
+            // issued before the first is used
+            auto parts_sum = [&](int p, int e, int h0) {
+                double v[kMaxParts];
+#pragma unroll
+                for (int hh = 0; hh < kMaxParts; ++hh)
+                    v[hh] = hh >= h0 && hh < NP ? load_dev(xslot(hh, p) + e) : 0.0;
+                double sum = 0.0;
+#pragma unroll
+                for (int hh = 0; hh < kMaxParts; ++hh)
+                    if (hh >= h0 && hh < NP) sum += v[hh];
+                return sum;
+            };
             auto unpair = [&](int p) {
                 paired = false;
                 if (half > 0) return true;
-                for (int e = tid; e < k * CS; e += NT) {
-                    double add = 0.0;
-                    for (int hh = 1; hh < NP; ++hh) add += load_dev(xslot(hh, p) + e);
-                    L.psum[e] += add;
-                }
+                for (int e = tid; e < k * CS; e += NT) L.psum[e] += parts_sum(p, e, 1);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __syncthreads();
                 return false;
-            };
-            // the sum over the sample's parts (part order, identical in every
-            // part) of element e of the pass-p slots
-            auto parts_sum = [&](int p, int e) {
-                double v = 0.0;
-                for (int hh = 0; hh < NP; ++hh) v += load_dev(xslot(hh, p) + e);
-                return v;
             };
             bool left = false;
             for (;;) {
@@ -776,8 +779,6 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
                                 if (prev >= 0) lds_add(pw + (prev * CS + D), -1.0);
                                 // read by the first workgroup if a shared
                                 // sample ends: device-coherent while shared
-                                // read by the first workgroup if a shared
-                                // sample ends: device-coherent while shared
                                 if (SHARE && paired)
                                     store_dev(lprev + (unsigned)i, am);
                                 else
@@ -854,26 +855,57 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
                 __syncthreads();
                 // A shared sample's workgroups exchange their partial sums
                 // (in the first pass also their shares of Q) through
-                // device-coherent stores and loads, and each adds all parts'
-                // in part order: every part then holds the same objective and
+                // device-coherent stores and loads: every part publishes its
+                // running sums; after a first barrier part h adds up the h-th
+                // P-th of the elements over all parts (in part order),
+                // publishes these totals and its share of the objective's
+                // centroid term; after a second barrier every part reads the
+                // totals.  Every part then holds the same objective and
                 // centroids.
-                bool xch = false;  // this pass's totals come from the slots
+                bool xch = false;  // this pass's totals come from the exchange
+                const int E = k * CS;
+                double* const tot = xslot(NP, it);
+                auto arrive = [&](int target) {
+                    if (tid == 0) L.ints[14] = parts_barrier(pflags, NP, target);
+                    __syncthreads();
+                    return __builtin_amdgcn_readfirstlane(L.ints[14]) != 0;
+                };
                 if (paired) {
                     double* mine = xslot(half, it);
-                    for (int e = tid; e < k * CS; e += NT) {
+                    for (int e = tid; e < E; e += NT) {
                         double S = 0.0;
-                        for (int gg = 0; gg < copies; ++gg) S += L.psum[(size_t)gg * k * CS + e];
+                        for (int gg = 0; gg < copies; ++gg) S += L.psum[(size_t)gg * E + e];
                         store_dev(mine + e, S);
                     }
                     if (first) {
                         fl = block_sum<NT>(fl, L.red);  // this workgroup's share of Q
-                        if (tid == 0) store_dev(mine + k * CS, fl);
+                        if (tid == 0) store_dev(mine + E, fl);
                     }
                     wait_stores();
                     __syncthreads();
-                    if (tid == 0) L.ints[14] = parts_barrier(pflags, NP, it + 1);
-                    __syncthreads();
-                    const bool arrived = __builtin_amdgcn_readfirstlane(L.ints[14]) != 0;
+                    bool arrived = arrive(2 * it + 1);
+                    if (arrived) {
+                        const int lo = (int)((int64_t)E * half / NP);
+                        const int hi = (int)((int64_t)E * (half + 1) / NP);
+                        double fph = 0.0;
+                        for (int e = lo + tid; e < hi; e += NT) {
+                            const int j = e / CS, t = e % CS;
+                            const double S = parts_sum(it, e, 0);
+                            store_dev(tot + e, S);
+                            if (t < d) {
+                                const double n = parts_sum(it, j * CS + D, 0);
+                                if (n > 0.0) {
+                                    const double dc = L.C64[e] - L.ref[t];
+                                    fph = __fma_rn(dc, __fma_rn(n, dc, -2.0 * S), fph);
+                                }
+                            }
+                        }
+                        fph = block_sum<NT>(fph, L.red);
+                        if (tid == 0) store_dev(mine + E + 1, fph);
+                        wait_stores();
+                        __syncthreads();
+                        arrived = arrive(2 * it + 2);
+                    }
                     if (!arrived) {
                         // a partner never came: abandon the sample
                         // (f = NaN, passes = -1)
@@ -886,32 +918,32 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
                     xch = true;
                 }
                 double fp = 0.0;
-                for (int e = tid; e < k * CS; e += NT) {
-                    const int j = e / CS, t = e % CS;
-                    if (t >= d) continue;
-                    double S = 0.0, n = 0.0;
-                    if (xch) {
-                        S = parts_sum(it, e);
-                        n = parts_sum(it, j * CS + D);
-                    } else {
+                if (xch) {
+                    // (the same loads in every thread: a uniform value)
+                    fp = parts_sum(it, E + 1, 0);
+                    if (first) Qr = parts_sum(it, E, 0);
+                } else {
+                    for (int e = tid; e < E; e += NT) {
+                        const int j = e / CS, t = e % CS;
+                        if (t >= d) continue;
+                        double S = 0.0, n = 0.0;
                         for (int gg = 0; gg < copies; ++gg) {
-                            S += L.psum[(size_t)gg * k * CS + e];
-                            n += L.psum[(size_t)gg * k * CS + j * CS + D];
+                            S += L.psum[(size_t)gg * E + e];
+                            n += L.psum[(size_t)gg * E + j * CS + D];
+                        }
+                        if (n > 0.0) {
+                            const double dc = L.C64[e] - L.ref[t];
+                            fp = __fma_rn(dc, __fma_rn(n, dc, -2.0 * S), fp);
                         }
                     }
-                    if (n > 0.0) {
-                        const double dc = L.C64[e] - L.ref[t];
-                        fp = __fma_rn(dc, __fma_rn(n, dc, -2.0 * S), fp);
+                    if (first) {
+                        double v2[2] = {fl, fp};
+                        block_sum_n<NT, 2>(v2, L.red);
+                        Qr = v2[0];
+                        fp = v2[1];
+                    } else {
+                        fp = block_sum<NT>(fp, L.red);
                     }
-                }
-                if (first && !xch) {
-                    double v2[2] = {fl, fp};
-                    block_sum_n<NT, 2>(v2, L.red);
-                    Qr = v2[0];
-                    fp = v2[1];
-                } else {
-                    fp = block_sum<NT>(fp, L.red);
-                    if (first) Qr = parts_sum(it, k * CS);
                 }
                 f = Qr + fp;
                 if (!(f > kSumsObjectiveMin * Qr)) {
@@ -942,21 +974,38 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
                 ++it;
                 if (it >= a.max_iter || f == 0.0 || (f_prev - f) < a.rel_tol * f_prev) break;
                 f_prev = f;
-                for (int e = tid; e < k * CS; e += NT) {
-                    const int j = e / CS, t = e % CS;
-                    double sum = 0.0, n = 0.0;
-                    if (xch) {
-                        sum = parts_sum(it - 1, e);
-                        n = parts_sum(it - 1, j * CS + D);
-                    } else {
-                        for (int gg = 0; gg < copies; ++gg) {
-                            sum += L.psum[(size_t)gg * k * CS + e];
-                            n += L.psum[(size_t)gg * k * CS + j * CS + D];
+                if (xch) {
+                    // the totals of pass it - 1, four elements per thread at
+                    // a time with their loads in flight together
+                    for (int e0 = tid; e0 < E; e0 += 4 * NT) {
+                        double sv[4], nv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = min(e0 + u * NT, E - 1);
+                            sv[u] = load_dev(tot + e);
+                            nv[u] = load_dev(tot + (e / CS) * CS + D);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = e0 + u * NT, t = e % CS;
+                            if (e >= E) break;
+                            double v = 0.0;
+                            if (t < d) v = nv[u] > 0.0 ? L.ref[t] + sv[u] / nv[u] : __builtin_nan("");
+                            L.C64[e] = v;
                         }
                     }
-                    double v = 0.0;
-                    if (t < d) v = n > 0.0 ? L.ref[t] + sum / n : __builtin_nan("");
-                    L.C64[e] = v;
+                } else {
+                    for (int e = tid; e < E; e += NT) {
+                        const int j = e / CS, t = e % CS;
+                        double sum = 0.0, n = 0.0;
+                        for (int gg = 0; gg < copies; ++gg) {
+                            sum += L.psum[(size_t)gg * E + e];
+                            n += L.psum[(size_t)gg * E + j * CS + D];
+                        }
+                        double v = 0.0;
+                        if (t < d) v = n > 0.0 ? L.ref[t] + sum / n : __builtin_nan("");
+                        L.C64[e] = v;
+                    }
                 }
                 __syncthreads();
             }

@@ -38,17 +38,20 @@ def store(db: dict, path: str | None = None) -> None:
     os.replace(tmp, p)
 
 
-def tuned(plan, X, idx, C, *, path: str | None = None, max_iter: int = 3, retune: bool = False):
+def tuned(plan, X, idx, C, *, path: str | None = None, max_iter: int = 3, rel_tol: float = 0.0,
+          retune: bool = False):
     """Give ``plan`` its cached configuration, or autotune it on (X, idx, C)
-    and cache the result.  Returns (config dict, measured ms or None)."""
+    (Lloyd from C with max_iter and rel_tol) and cache the result.  Returns
+    (config dict, measured ms or None)."""
     key = plan.tune_key()
     db = load(path)
     ent = db.get(key)
     if ent is not None and not retune:
-        cfg = {k: int(ent.get(k, 0)) for k in ("wg_per_cu", "copies", "order", "seed_team", "seed_inflight")}
+        cfg = {k: int(ent.get(k, 0)) for k in ("wg_per_cu", "copies", "order", "seed_team", "seed_inflight",
+                                             "parts")}
         plan.set_tune(**cfg)
         return cfg, None
-    t, ms = plan.autotune(X, idx, C, max_iter=max_iter)
+    t, ms = plan.autotune(X, idx, C, max_iter=max_iter, rel_tol=rel_tol)
     cfg = t.as_dict()
     db[key] = dict(cfg, ms=ms)
     try:

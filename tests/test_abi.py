@@ -110,7 +110,7 @@ def test_plan_validation(L):
     _err(L, L.hpc_plan_create(4, _desc((5, 0, 10, 3)), 1, 10, 12, 0, ct.byref(h)))  # idx range
     _err(L, L.hpc_plan_create(4, good, 0, 10, 12, 0, ct.byref(h)))           # no samples
     assert h.value is None
-    t = _lib.Tune(0, 0, 0, 0, 0)
+    t = _lib.Tune(0, 0, 0, 0, 0, 0)
     _err(L, L.hpc_plan_set_tune(None, ct.byref(t)))
     _err(L, L.hpc_plan_get_tune(None, ct.byref(t)))
     _err(L, L.hpc_plan_replay(None, 1, None))
@@ -142,9 +142,10 @@ def test_tuning_cache_roundtrip(tmp_path):
 
     fp = FakePlan()
     cfg, ms = tuning.tuned(fp, None, None, None, path=p)
-    # an entry written before the seeding team size was tuned reads as 0 (auto)
+    # an entry written before the seeding team size and the parts per
+    # sample were tuned reads them as 0 (automatic)
     assert ms is None and fp.cfg == {"wg_per_cu": 2, "copies": 4, "order": 0, "seed_team": 0,
-                                  "seed_inflight": 0}
+                                  "seed_inflight": 0, "parts": 0}
 
 
 def test_plan_draw_advance_validation(L):

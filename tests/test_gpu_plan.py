@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import synthetic
-from tests.tolerances import F_REL, assert_centroids, diag_clean, rel
+from tests.tolerances import F_REL, assert_centroids, assert_labels, diag_clean, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,56 @@ def _dn(desc):
 CONFIGS = [dict(), dict(wg_per_cu=1, copies=1, order=0), dict(wg_per_cu=2, copies=4, order=1),
            dict(wg_per_cu=0, copies=2, order=1)]
 
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+@pytest.mark.parametrize("d,n,s,parts", [(32, 40, 8192, 8), (64, 24, 16384, 16), (64, 30, 4096, 4)])
+def test_plan_parts_beyond_the_resident_grid(hp, orc, prec, d, n, s, parts):
+    """More samples x parts than resident workgroups (one per CU): the
+    samples run in turn, each on `parts` workgroups, later ones from the
+    queue as earlier ones finish; two samples start with a centroid far from
+    every point, reseed in the first pass and finish alone (their other
+    parts take queued tasks early).  Every configuration gives the pass
+    counts and labels of the automatic one and of the oracle."""
+    m, k = 100_000, 12
+    mx = synthetic.gaussian_mixture(m, d, k, seed=90 + d, centre_box=10.0, std=1.0)
+    Xn, centres = mx.X.numpy(), mx.centres.numpy()
+    rng = np.random.default_rng(d + n)
+    C0 = np.stack([centres + rng.normal(0, 0.6, (k, d)) for _ in range(n)]).astype(np.float32)
+    C0[3, 5] = 1e4
+    C0[n - 2, 0] = -1e4
+    Xg = mx.X.cuda()
+    desc, idx_len, c_len = hp.make_desc([s] * n, [k] * n, seed=9, sample_id=np.arange(n), d=d)
+    idx = hp.draw_samples(m, desc, idx_len)
+    idx_n = idx.cpu().numpy()
+    outs = []
+    with hp.Plan(d, desc, idx_len, c_len, precision=prec) as plan:
+        for cfg in (dict(), dict(wg_per_cu=1, parts=parts), dict(wg_per_cu=1, parts=2, copies=1)):
+            plan.set_tune(**cfg)
+            assert plan.tune.parts == cfg.get("parts", 0)
+            C = torch.from_numpy(C0.ravel().copy()).cuda()
+            f, it, lab = plan.lloyd(Xg, idx, C, want_labels=True)
+            outs.append((C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()))
+    (Cg, fg, itg, lg) = outs[0]
+    assert np.isfinite(fg).all() and (itg > 0).all()
+    for Co, fo, ito, lo in outs[1:]:
+        # configurations differ only in the order the partial sums are added
+        assert np.array_equal(itg, ito) and np.array_equal(lg, lo)
+        assert np.allclose(fg, fo, rtol=1e-11, atol=0) and np.allclose(Cg, Co, rtol=1e-6, atol=1e-6)
+    checked = 0
+    for b in range(n):
+        ib = idx_n[b * s:(b + 1) * s]
+        ro = orc.lloyd(Xn, ib, k, C0[b].astype(np.float64), seed=9, sample_id=b, want_margins=True)
+        if b in (3, n - 2):
+            assert ro.diag["n_seed_calls"] >= 1
+        if not diag_clean(ro.diag):
+            continue
+        checked += 1
+        for Co, fo, ito, lo in outs:
+            assert ito[b] == ro.iters and rel(fo[b], ro.f) <= F_REL, (b, ito[b], ro.iters)
+            assert_centroids(Co[b * k * d:(b + 1) * k * d].reshape(k, d), ro.C, Xn[ib])
+            assert_labels(lo[b * s:(b + 1) * s], ro.labels, ro.margins)
+    assert checked >= n // 2
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_plan_lloyd_every_config_matches_oracle(hp, orc, prec):
