@@ -72,6 +72,12 @@ def parse():
     ap.add_argument("--tts-rounds", type=int, default=4, help="rounds of each batched form")
     ap.add_argument("--train-pairs", type=int, default=50_000,
                     help="training pairs of the learned initializer (0: skip the learned form)")
+    ap.add_argument("--train-epochs", type=int, default=8,
+                    help="epochs over the training pairs of the learned initializer")
+    ap.add_argument("--train-batch", type=int, default=64, help="samples per gradient step")
+    ap.add_argument("--train-lr", type=float, default=2e-3, help="peak Adam learning rate")
+    ap.add_argument("--eval-samples", type=int, default=1024,
+                    help="held-out cold samples of the learned initializer's evaluation")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the default launch configuration instead of autotuning")
     ap.add_argument("--pmc-target", action="store_true",
@@ -124,9 +130,14 @@ def main():
         cpu = cpu_baseline(X, main_res["C_before"], main_res["r_first_timed"], args, m, d, W, s,
                            k)
     out["cpu_baseline"] = cpu
+    model = None
+    if args.workload == "metric" and args.train_pairs > 0:
+        model, out["learned_init"] = learned_init(api, args, d, k, s)
     if args.tts:
         f_ref = cpu["time_to_sse_reference"]["f_ref"] if cpu else None
-        out["time_to_sse"] = time_to_sse(api, X, args, m, d, k, s, W, f_ref)
+        out["time_to_sse"] = time_to_sse(api, X, args, m, d, k, s, W, f_ref, model)
+    if model is not None:
+        model.close()
     if args.workload == "metric" and args.precision_leg:
         # the precision workload (m = 1e8, d = 64, k = 100, 128 workers of
         # 50,000, BF16x3) in the same run: its MFMA and HBM rooflines and its
@@ -631,18 +642,95 @@ def _first_reach(sses, times, target):
     return None, None, sses[-1] if sses else None
 
 
-def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
+def learned_init(api, args, d, k, s):
+    """The learned initializer on its own family (25-component mixtures in
+    d = 32 with fresh random centres, s = 10,000 points per sample): pairs
+    made by the method (cold K-means++ plus Lloyd on each whole sample; the
+    encoder reads its first n_enc points), several epochs of Adam with a
+    warm-up and cosine schedule and the held-out loss after every epoch,
+    then an evaluation on fresh cold samples against K-means++ (acceptance,
+    Lloyd passes to the stop rule, final sample objective).  Returns (model,
+    report)."""
+    import torch
+
+    import synthetic
+    from paper_2311_04517_amd import learned
+
+    dev = "cuda"
+    pool, n_enc, batch = 1024, 1024, args.train_batch
+    t0 = time.perf_counter()
+    train, held = learned.Pairs(d, k, n_enc), learned.Pairs(d, k, n_enc)
+    n_pools = -(-args.train_pairs // pool)
+    for q in range(n_pools + 1):  # the last pool is held out
+        n_q = pool if q == n_pools else min(pool, args.train_pairs - q * pool)
+        Xp, _ = synthetic.mixture_family(n_q, s, d=d, n_comp=k, seed=100_000 + q, device=dev)
+        desc_p, _, c_len_p = api.make_desc([s] * n_q, [k] * n_q, seed=q, sample_id=range(n_q),
+                                           d=d)
+        idx_p = torch.arange(n_q * s, dtype=torch.int64, device=dev)
+        T, _, _ = learned.method_targets(Xp, idx_p, desc_p, c_len_p)
+        (held if q == n_pools else train).add(Xp, idx_p, desc_p, T)
+        del Xp, idx_p, T
+    train.finish()
+    held.finish()
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    print(f"[bench] learned init: {train.n} training pairs, {held.n} held out "
+          f"({t_pairs:.1f}s)", file=sys.stderr, flush=True)
+    model = api.SetEncoder(d, k, n_enc=n_enc, max_batch=batch, seed=args.seed)
+    t1 = time.perf_counter()
+    def progress(c):
+        print(f"[bench] learned init: epoch {c['epoch']}, train loss {c['train']:.4f}, "
+              f"held-out {c['heldout']:.4f} ({time.perf_counter() - t1:.1f}s)", file=sys.stderr,
+              flush=True)
+
+    curve = learned.fit(model, train, held, epochs=args.train_epochs, batch=batch,
+                        lr=args.train_lr, lr_min=args.train_lr / 100, warmup=200, seed=args.seed,
+                        on_epoch=progress)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t1
+    print(f"[bench] learned init: {args.train_epochs} epochs in {t_fit:.1f}s; held-out loss "
+          + " ".join(f"{c['heldout']:.4f}" for c in curve), file=sys.stderr, flush=True)
+    n_train = train.n
+    del train, held
+    n_eval = args.eval_samples
+    Xe, _ = synthetic.mixture_family(n_eval, s, d=d, n_comp=k, seed=900_000, device=dev)
+    desc_e, _, c_len_e = api.make_desc([s] * n_eval, [k] * n_eval, seed=args.seed + 7,
+                                       sample_id=range(n_eval), d=d)
+    idx_e = torch.arange(n_eval * s, dtype=torch.int64, device=dev)
+    ev = learned.evaluate(model, Xe, idx_e, desc_e, c_len_e, precision=api.PREC_FP32)
+    summ = learned.summarize(ev)
+    del Xe, idx_e
+    print(f"[bench] learned init: accepted {summ['accepted_frac']:.3f}, passes learned "
+          f"{summ['learned']['passes_mean']:.2f} vs K-means++ {summ['kmeanspp']['passes_mean']:.2f}, "
+          f"final objective ratio {summ['learned']['final_f_over_kmeanspp_mean']:.6f}",
+          file=sys.stderr, flush=True)
+    rep = {"family": f"25-component Gaussian mixtures, fresh centres U[-20,20]^{d}, diagonal std "
+                     f"U[0.5,3], s={s}, k={k}",
+           "pairs": n_train, "heldout_pairs": pool, "n_enc": n_enc, "epochs": args.train_epochs,
+           "batch": batch,
+           "schedule": f"Adam, linear warm-up over 200 steps to {args.train_lr:g}, cosine decay "
+                       f"to {args.train_lr / 100:g}",
+           "seconds_pairs": t_pairs, "seconds_training": t_fit,
+           "curve": [{kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in c.items()}
+                     for c in curve],
+           "eval": dict(summ, what="fresh cold samples of the family: seeds chosen by "
+                                   "hpc_learned_seed (proposal where its sample objective is "
+                                   "no larger than K-means++'s), Lloyd (FP32 screening) to the "
+                                   "stop rule from them, from the K-means++ seeds, and from the "
+                                   "raw proposals")}
+    return model, rep
+
+
+def time_to_sse(api, X, args, m, d, k, s, W, f_ref, model=None):
     """Time until the incumbent's full-data SSE is within 1e-3 of the
     reference f_ref, for the plain single-worker form on the GPU and for
     batched forms (W workers per round: FP32, BF16 screening, BF16 plus the
     learned initializer on the cold round).  Each form records an HIP event
     and a copy of its incumbent after every incumbent update; SSEs are
-    evaluated afterwards."""
+    evaluated afterwards.  ``model``: the trained learned initializer (its
+    form is skipped without one)."""
     import numpy as np
     import torch
-
-    import synthetic
-    from paper_2311_04517_amd import learned
 
     dev = X.device
     stream = torch.cuda.current_stream()
@@ -681,26 +769,6 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
     i, t, v = _first_reach(sses, t_plain, target)
     res["plain_fp32_per_sample"] = {"ms": t, "samples": None if i is None else i + 1,
                                     "sse": v, "ms_all": t_plain[-1]}
-
-    model = None
-    if args.train_pairs > 0:
-        # the learned initializer, trained on method-generated pairs of the
-        # same family of mixtures (fresh 25-component mixtures in d = 32)
-        t0 = time.perf_counter()
-        model = api.SetEncoder(d, k, n_enc=1024, max_batch=32, seed=args.seed)
-        pool = 1024
-        n_pools = max(1, args.train_pairs // pool)
-        for q in range(n_pools):
-            Xp, _ = synthetic.mixture_family(pool, s, d=d, n_comp=k, seed=100_000 + q, device=dev)
-            desc_p, idx_len_p, c_len_p = api.make_desc([s] * pool, [k] * pool, seed=q,
-                                                       sample_id=range(pool), d=d)
-            idx_p = torch.arange(pool * s, dtype=torch.int64, device=dev)
-            T, _, _ = learned.method_targets(Xp, idx_p, desc_p, c_len_p)
-            learned.train(model, Xp, idx_p, desc_p, T, steps=pool // 32, batch=32,
-                          lr=2e-3 * 0.9 ** q, seed=q)
-            del Xp, idx_p, T
-        torch.cuda.synchronize()
-        res["learned_training"] = {"pairs": n_pools * pool, "seconds": time.perf_counter() - t0}
 
     forms = [("batched_fp32", api.PREC_FP32, False), ("batched_bf16", api.PREC_BF16_MFMA, False)]
     if model is not None:
@@ -746,8 +814,6 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref):
     best = res.get("batched_bf16_learned") or res["batched_bf16"]
     p = res["plain_fp32_per_sample"]["ms"]
     res["speedup_vs_plain"] = (p / best["ms"]) if (p and best["ms"]) else None
-    if model is not None:
-        model.close()
     return res
 
 

@@ -471,49 +471,84 @@ __global__ __launch_bounds__(H) void k_enc_head_dp(const float* __restrict__ Whr
 
 // ---------------------------------------------------------------------------
 // Weight gradient C = A^T B over P rows (A: P x lda, its first M columns;
-// B: P x N, row stride ldb), FP32, 64 x 64 output tiles of 4 x 4 per
-// thread, rows staged 32 at a time through LDS; split over P (grid.z), each
-// split writing its own partial [z][M][N].
+// B: P x N, row stride ldb) on the matrix cores: the operands are rounded
+// to BF16 (as the forward's are), products accumulate in FP32.  One
+// workgroup of four waves per 64 x 64 output tile, each wave a 32 x 32
+// quarter (2 x 2 blocks of v_mfma_f32_16x16x32_bf16).  The contraction runs
+// over the rows p: per stage 128 rows of A's and B's 64 columns go to LDS
+// transposed (column-major, p contiguous), so that a lane's eight K values
+// of the MFMA operand (rows 8g .. 8g+7 of its column, g = lane / 16) are one
+// 16-byte read.  Split over P (grid.z), each split writing its own partial
+// [z][M][N].
 // ---------------------------------------------------------------------------
+constexpr int WG_ROWS = 128;              // rows of p per LDS stage
+constexpr int WG_PAD = WG_ROWS + 8;       // LDS column stride (BF16): 272 B
+
 __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ A, int32_t lda, int32_t M,
                                                const float* __restrict__ Bm, int32_t ldb, int32_t N,
                                                int64_t P, int64_t per_split,
                                                float* __restrict__ part) {
-    __shared__ float As[32][64];
-    __shared__ float Bs[32][64];
+    __shared__ __align__(16) __bf16 As[64 * WG_PAD];
+    __shared__ __align__(16) __bf16 Bs[64 * WG_PAD];
     const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
     const int64_t p0 = blockIdx.z * per_split;
     const int64_t p1 = p0 + per_split < P ? p0 + per_split : P;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    float acc[4][4] = {};
-    for (int64_t pb = p0; pb < p1; pb += 32) {
-        for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-            const int r = e / 64, col = e % 64;
-            const int64_t p = pb + r;
-            As[r][col] = (p < p1 && m0 + col < M) ? A[p * lda + m0 + col] : 0.f;
-            Bs[r][col] = (p < p1 && n0 + col < N) ? Bm[p * ldb + n0 + col] : 0.f;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;  // this wave's quarter
+    const int col = lane & 15, g = lane >> 4;
+    // staging: thread (c, q) moves column c of rows 2i, 2i + 1 for i in
+    // [16q, 16q + 16), two BF16 per 32-bit LDS store
+    const int c = tid & 63, q = tid >> 6;
+    const bool a_ok = m0 + c < M, b_ok = n0 + c < N;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t pb = p0; pb < p1; pb += WG_ROWS) {
+        float av[32], bv[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int64_t p = pb + 32 * q + u;
+            av[u] = (p < p1 && a_ok) ? A[p * lda + m0 + c] : 0.f;
+            bv[u] = (p < p1 && b_ok) ? Bm[p * ldb + n0 + c] : 0.f;
+        }
+        __syncthreads();  // the previous stage's operand reads are done
+#pragma unroll
+        for (int u = 0; u < 32; u += 2) {
+            const int r = 32 * q + u;
+            __bf16 pa[2] = {(__bf16)av[u], (__bf16)av[u + 1]};
+            __bf16 pbv[2] = {(__bf16)bv[u], (__bf16)bv[u + 1]};
+            *reinterpret_cast<uint32_t*>(&As[c * WG_PAD + r]) = *reinterpret_cast<uint32_t*>(pa);
+            *reinterpret_cast<uint32_t*>(&Bs[c * WG_PAD + r]) = *reinterpret_cast<uint32_t*>(pbv);
         }
         __syncthreads();
-#pragma unroll 4
-        for (int r = 0; r < 32; ++r) {
-            const float4 av = *reinterpret_cast<const float4*>(&As[r][ty * 4]);
-            const float4 bv = *reinterpret_cast<const float4*>(&Bs[r][tx * 4]);
-            const float aa[4] = {av.x, av.y, av.z, av.w}, bb[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+        for (int kb = 0; kb < WG_ROWS; kb += 32) {
+            bf16x8 ao[2], bo[2];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __fmaf_rn(aa[i], bb[j], acc[i][j]);
+            for (int i = 0; i < 2; ++i) {
+                ao[i] = *reinterpret_cast<const bf16x8*>(&As[(wm + 16 * i + col) * WG_PAD + kb + 8 * g]);
+                bo[i] = *reinterpret_cast<const bf16x8*>(&Bs[(wn + 16 * i + col) * WG_PAD + kb + 8 * g]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao[i], bo[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
+    // lane (col, g) holds rows 4g .. 4g + 3 of column col of each block
     float* out = part + (size_t)blockIdx.z * M * N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int mm = m0 + ty * 4 + i, nn = n0 + tx * 4 + j;
-            if (mm < M && nn < N) out[(size_t)mm * N + nn] = acc[i][j];
-        }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int mm = m0 + wm + 16 * i + 4 * g + r, nn = n0 + wn + 16 * j + col;
+                if (mm < M && nn < N) out[(size_t)mm * N + nn] = acc[i][j][r];
+            }
 }
 
 // Column sums of B (P x N, stride ldb), split over P: part[z][N].
