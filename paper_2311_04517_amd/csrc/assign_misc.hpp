@@ -4,6 +4,7 @@
 
 #include "common.hpp"
 #include "mfma_screen.hpp"
+#include "screen32.hpp"
 
 namespace hpc {
 
@@ -207,6 +208,148 @@ __global__ __launch_bounds__(NT, NT > 256 ? NT / 256 : (D <= 32 ? 5 : (D <= 64 ?
         }
     }
     const double tot = block_sum<NT>(fl, red);
+    if (tid == 0) partials[blockIdx.x] = tot;
+    if (counts)
+        for (int j = tid; j < k; j += NT)
+            if (hist[j]) atomicAdd(&counts[j], (unsigned long long)hist[j]);
+}
+
+// Bytes of k_assign_sse32's LDS: FP64 centroids, operand tables and biases
+// for blocks of 32, valid flags and histogram, wave partials.
+template <int D, int PREC>
+__host__ __device__ inline size_t assign32_lds_bytes(int k, int nt) {
+    const int nb = (k + 31) / 32;
+    size_t b = (((size_t)k * Lay32<D>::CS * 8 + 15) / 16) * 16;
+    b += ((aop32_bytes<D, PREC>(nb) + 15) / 16) * 16 + (size_t)nb * 128;
+    b += (((size_t)k * 8 + 15) / 16) * 16;  // valid + hist
+    b += (size_t)nt * 8;                    // per-thread objective shares
+    b += (size_t)(nt / kWave) * 8 + 16;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Full assignment for rows of up to 32 coordinates on 32 x 32 tiles
+// (screen32.hpp): the same results as k_assign_sse (labels, counts, FP64
+// objective share per workgroup), each wave taking tiles of 32 rows, every
+// row in two lanes.
+// ---------------------------------------------------------------------------
+template <int D, int NT, int PREC>
+__global__ __launch_bounds__(NT, 4) void k_assign_sse32(const float* __restrict__ X, int64_t m,
+                                                        int d, const float* __restrict__ C, int k,
+                                                        int32_t* __restrict__ labels,
+                                                        unsigned long long* __restrict__ counts,
+                                                        double* __restrict__ partials, bool vec) {
+    extern __shared__ __align__(16) char smem[];
+    constexpr int DH = Lay32<D>::DH, CS = Lay32<D>::CS;
+    constexpr int NW = NT / kWave;
+    const int nb = (k + 31) / 32;
+    char* p = smem;
+    double* C64 = reinterpret_cast<double*>(p);
+    p += (((size_t)k * CS * 8 + 15) / 16) * 16;
+    void* aop = p;
+    p += ((aop32_bytes<D, PREC>(nb) + 15) / 16) * 16;
+    float* nrm = reinterpret_cast<float*>(p);
+    p += (size_t)nb * 128;
+    int* hist = reinterpret_cast<int*>(p);
+    int* flag = hist + k;
+    p += (((size_t)k * 8 + 15) / 16) * 16;
+    // each thread's running share of the objective lives in LDS: held in a
+    // register across the tile loop it is the value the allocator spills,
+    // and a scratch reload waits for every row load in flight
+    double* share = reinterpret_cast<double*>(p);
+    p += (size_t)NT * 8;
+    double* red = reinterpret_cast<double*>(p);
+    const int tid = threadIdx.x, lane = tid & 63, hh = lane >> 5;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
+    for (int e = tid; e < k * CS; e += NT) {
+        const int j = e / CS, t = e % CS;
+        C64[e] = t < d ? (double)C[(int64_t)j * d + t] : 0.0;
+    }
+    for (int j = tid; j < k; j += NT) hist[j] = 0;
+    share[tid] = 0.0;
+    unsigned long long* const mx2 = reinterpret_cast<unsigned long long*>(red + NW);
+    if (tid == 0) {
+        flag[0] = 0;
+        *mx2 = 0ull;
+    }
+    __syncthreads();
+    for (int j = tid; j < k; j += NT) {
+        if (C64[j * CS] != C64[j * CS]) continue;
+        double n2 = 0.0;
+        for (int t = 0; t < d; ++t) n2 = __fma_rn(C64[j * CS + t], C64[j * CS + t], n2);
+        atomicAdd(&flag[0], 1);
+        atomicMax(mx2, (unsigned long long)__double_as_longlong(n2));
+    }
+    build_operands32<D, PREC, NT>(C64, k, d, nb, aop, nrm);
+    __syncthreads();
+    const int n_valid = flag[0];
+    double alpha, beta;
+    screen_coeffs<PREC>(d, &alpha, &beta);
+    const double cmax = sqrt(__longlong_as_double((long long)*mx2));
+    const float ea = (float)(alpha * cmax), eb = (float)(beta * cmax * cmax);
+    unsigned kmask;
+    float qscale;
+    key_params(2 * nb, &kmask, &qscale);
+    const int64_t n_tiles = (m + 31) / 32;
+    auto process = [&](int64_t tile, const float (&xh)[DH]) {
+        const int64_t i = tile * 32 + (lane & 31);
+        const bool valid = i < m;
+        const float xn2 = point_norm2_32<D>(xh);
+        const float xn = cert_norm(xn2);
+        const float h = screen_shift(xn2, xn, ea, eb);
+        const Top3 t3 = screen_tile32<D, PREC>(xh, aop, nrm, nb, h, kmask);
+        const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
+        const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
+        int am = redecide64_32<D, PREC>(xh, t3, !ok, top2_suffices(t3, kmask, qscale, xn, ea, eb),
+                                        a1 < k ? a1 : 0, a2 < k ? a2 : 0, C64, aop, nrm, nb, h,
+                                        kmask, qscale, xn, ea, eb);
+        if (valid) {
+            share[tid] += n_valid > 0 ? half_part64<D>(xh, C64 + am * CS) : __builtin_huge_val();
+            if (n_valid == 0) am = -1;
+            if (hh == 0) {
+                if (labels) labels[i] = am;
+                if (counts && am >= 0) atomicAdd(&hist[am], 1);
+            }
+        }
+    };
+    const int64_t first = (int64_t)blockIdx.x * NW + wid, stride = (int64_t)gridDim.x * NW;
+    if (vec) {
+        // rows of D floats, 16-byte aligned: three register buffers, rows of
+        // the next two tiles in flight while one is processed; rows past the
+        // end re-read the last row, tiles past the end are skipped by
+        // wave-uniform guards
+        // the tile's base row is wave-uniform (scalar registers) and the
+        // lane's row a 32-bit offset from it, so no per-lane 64-bit address
+        // is kept across the tile
+        auto fetch = [&](int64_t tile, float (&dst)[DH]) {
+            const int64_t r0 = min(tile * 32, m - 1);  // wave-uniform
+            const int row = (int)min((int64_t)(lane & 31), m - 1 - r0);
+            load_half<D>(X + r0 * D + row * D, hh, dst);
+        };
+        float xa[DH], xb[DH], xc[DH];
+        fetch(first, xa);
+        fetch(first + stride, xb);
+        for (int64_t tile = first; tile < n_tiles; tile += 3 * stride) {
+            fetch(tile + 2 * stride, xc);
+            process(tile, xa);
+            fetch(tile + 3 * stride, xa);
+            if (tile + stride < n_tiles) process(tile + stride, xb);
+            fetch(tile + 4 * stride, xb);
+            if (tile + 2 * stride < n_tiles) process(tile + 2 * stride, xc);
+        }
+    } else {
+        for (int64_t tile = first; tile < n_tiles; tile += stride) {
+            const int64_t i = tile * 32 + (lane & 31);
+            float xh[DH];
+#pragma unroll
+            for (int t = 0; t < DH; ++t) {
+                const int dim = hh * DH + t;
+                xh[t] = (i < m && dim < d) ? X[i * d + dim] : 0.f;
+            }
+            process(tile, xh);
+        }
+    }
+    const double tot = block_sum<NT>(share[tid], red);
     if (tid == 0) partials[blockIdx.x] = tot;
     if (counts)
         for (int j = tid; j < k; j += NT)

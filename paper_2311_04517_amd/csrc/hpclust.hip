@@ -533,14 +533,62 @@ int launch_assign_nt(const float* X, int64_t m, int d, const float* C, int k, in
     return HPC_OK;
 }
 
-// Full assignment: 256-thread workgroups, or (d <= 64) 768-thread ones when
-// the centroid tables leave room for more resident waves that way.
+// The full assignment on 32-point tiles (rows of up to 32 coordinates):
+// 256-thread workgroups, four workgroup slots per resident one.
+template <int D, int PREC>
+int launch_assign32(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
+                    int64_t* counts, double* sse, const PartialsDst& pd, hipStream_t st,
+                    int lds_max) {
+    constexpr int NT = 256, NW = NT / hpc::kWave;
+    const size_t lds = hpc::assign32_lds_bytes<D, PREC>(k, NT);
+    if (lds > (size_t)lds_max)
+        return fail(HPC_ERR_UNSUPPORTED, "k=%d, padded d=%d: centroids exceed LDS", k, D);
+    auto kern = hpc::k_assign_sse32<D, NT, PREC>;
+    if (lds > 64 * 1024)
+        HPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    HPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds));
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc) return rc;
+    const int64_t want = (m + 32 * NW - 1) / (32 * NW);
+    const int64_t slots = (int64_t)cus * std::max(1, per_cu) * 4;
+    int64_t g64 = std::max<int64_t>(1, std::min<int64_t>(want, slots));
+    double* partials = nullptr;
+    if (pd.ws) {
+        rc = ws_reserve_dev(pd.ws, Carve::need({(size_t)g64 * 8}));
+        if (rc) return rc;
+        Carve cv(pd.ws->dev);
+        partials = static_cast<double*>(cv.take((size_t)g64 * 8));
+    } else {
+        g64 = std::min<int64_t>(g64, pd.cap);
+        partials = pd.fixed;
+    }
+    const int grid = (int)g64;
+    if (counts)
+        hipLaunchKernelGGL(hpc::k_fill_u64, dim3((k + 255) / 256), dim3(256), 0, st,
+                           reinterpret_cast<unsigned long long*>(counts), (int64_t)k, 0ull);
+    const bool vec = (d == D) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, X, m, d, C, k, labels,
+                       reinterpret_cast<unsigned long long*>(counts), partials, vec);
+    hipLaunchKernelGGL(hpc::k_reduce_partials<256>, dim3(1), dim3(256), 0, st, partials, grid,
+                       sse);
+    HPC_HIP(hipGetLastError());
+    return HPC_OK;
+}
+
+// Full assignment: up to d = 32 on 32-point tiles; wider rows on 16-point
+// tiles with 256-thread workgroups, or (d <= 64) 768- or 1,024-thread ones
+// when the centroid tables leave room for more resident waves that way.
 template <int D, int PREC>
 int launch_assign(const float* X, int64_t m, int d, const float* C, int k, int32_t* labels,
                   int64_t* counts, double* sse, const PartialsDst& w, hipStream_t st) {
     int lds_max = 0;
     int rc = max_dyn_lds(&lds_max);
     if (rc) return rc;
+    if constexpr (D <= 32)
+        return launch_assign32<D, PREC>(X, m, d, C, k, labels, counts, sse, w, st, lds_max);
     int w256 = 0, w768 = 0, w1024 = 0;
     rc = assign_waves_per_cu<D, 256, PREC>(hpc::assign_lds_bytes<D, PREC>(k, 256), lds_max, &w256);
     if (rc) return rc;

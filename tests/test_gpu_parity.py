@@ -370,15 +370,17 @@ def test_near_ties_are_redecided_exactly(hp, orc, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_crowded_centroids_are_rescanned_exactly(hp, orc, prec):
+@pytest.mark.parametrize("d", [16, 32, 64])
+def test_crowded_centroids_are_rescanned_exactly(hp, orc, prec, d):
     """Groups of four centroids 0.05 apart, far from the origin: for most
     points the three best screened keys are all within the screening error,
     so neither the winner nor the best two are certified and the decision
     goes to the FP64 rescan of every row the screening cannot exclude.
-    k = 100 leaves padding rows in the last block of 16, and a NaN row
-    inside a group must never be chosen."""
-    rng = np.random.default_rng(11)
-    d, groups, m = 64, 25, 30_000
+    k = 100 leaves padding rows in the last block (of 16, or of 32 for the
+    assignment's 32-point tiles at d <= 32), and a NaN row inside a group
+    must never be chosen."""
+    rng = np.random.default_rng(11 + d)
+    groups, m = 25, 30_000
     G = rng.uniform(-20, 20, size=(groups, d)) + 40.0
     Cn = (np.repeat(G, 4, axis=0) + rng.normal(0, 0.05, size=(4 * groups, d))).astype(np.float32)
     Cn[5] = np.nan
