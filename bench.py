@@ -22,8 +22,9 @@ rate (2 k d flop per sample-point-iter) against the BF16 MFMA peak.
 Every screening type (FP32, BF16, BF16x3) only proposes the nearest
 centroid; each decision is certified or re-taken in FP64, so pass counts,
 labels, centroids, f and SSE are the same for all three (the JSON line
-reports whether they were).  The default is the fastest type per workload:
-BF16 for the metric workload, BF16x3 for the precision one.
+reports whether they were).  The default is BF16x3, the fastest type on
+both workloads: it certifies nearly every point, so fewer tiles go to the
+FP64 re-decision than with plain BF16 screening.
 """
 from __future__ import annotations
 
@@ -62,7 +63,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", choices=list(SCREENINGS), default=None,
                     help="MFMA type of the distance screening (decisions are FP64-exact); "
-                         "default bf16 for the metric workload, bf16x3 for the precision one")
+                         "default bf16x3 (the fastest on both workloads)")
     ap.add_argument("--no-other-precision", dest="other_precision", action="store_false",
                     help="skip the same measurement with the other screening types")
     ap.add_argument("--no-tts", dest="tts", action="store_false",
@@ -158,7 +159,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-WORKLOADS = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="bf16"),
+WORKLOADS = {"metric": dict(m=10_000_000, workers=1024, s=10_000, k=25, precision="bf16x3"),
              "precision": dict(m=100_000_000, workers=128, s=50_000, k=100, precision="bf16x3")}
 
 
