@@ -47,8 +47,8 @@ SCREENINGS = {"fp32": (0, "f32+f64", 157.3), "bf16": (1, "bf16+f64", 2500.0),
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["metric", "precision"], default="metric",
                     help="metric: m = 1e7, d = 32, k = 25, 1,024 workers of 10,000 points "
                          "(the headline); precision: m = 1e8, d = 64, 100 rotated anisotropic "
