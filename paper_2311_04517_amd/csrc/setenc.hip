@@ -194,7 +194,9 @@ int wgrad(hpc_setenc s, const float* A, int lda, int M, const float* B, int ldb,
 }
 
 int colsum(hpc_setenc s, const float* B, int ldb, int N, int64_t P, float* out, hipStream_t st) {
-    const int splits = s->wsplits;
+    // about 128 rows per split (the partials buffer holds wsplits x H x
+    // max(H, kd) floats, far more than splits x N)
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(512, (P + 127) / 128));
     const int64_t per = (P + splits - 1) / splits;
     hipLaunchKernelGGL(enc::k_colsum, dim3((N + 255) / 256, splits), dim3(256), 0, st, B, ldb, N,
                        P, per, s->wpart);

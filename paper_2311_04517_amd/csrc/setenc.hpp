@@ -551,16 +551,25 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ A, int3
             }
 }
 
-// Column sums of B (P x N, stride ldb), split over P: part[z][N].
+// Column sums of B (P x N, stride ldb), split over P: part[z][N].  Four
+// rows per step with independent partial sums, so four loads are in flight
+// per thread.
 __global__ void k_colsum(const float* __restrict__ Bm, int32_t ldb, int32_t N, int64_t P,
                          int64_t per_split, float* __restrict__ part) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const int64_t p0 = blockIdx.y * per_split;
     const int64_t p1 = p0 + per_split < P ? p0 + per_split : P;
-    float s = 0.f;
-    for (int64_t p = p0; p < p1; ++p) s += Bm[p * ldb + n];
-    part[(size_t)blockIdx.y * N + n] = s;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int64_t p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        s0 += Bm[p * ldb + n];
+        s1 += Bm[(p + 1) * ldb + n];
+        s2 += Bm[(p + 2) * ldb + n];
+        s3 += Bm[(p + 3) * ldb + n];
+    }
+    for (; p < p1; ++p) s0 += Bm[p * ldb + n];
+    part[(size_t)blockIdx.y * N + n] = (s0 + s1) + (s2 + s3);
 }
 
 // out[e] = sum over splits of part[z][e] (fixed order).

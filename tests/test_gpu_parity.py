@@ -79,6 +79,29 @@ def test_assign_sse_parity(hp, orc, d, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("d", [8, 16, 32, 64])
+def test_assign_sse_unaligned_rows(hp, orc, d, prec):
+    """X starting 4 bytes past a 16-byte boundary takes the element-wise
+    row loads instead of the 16-byte ones: the same labels, counts and
+    objective, bit for bit, as on the aligned copy, and the oracle's."""
+    m, k = 40_003, 37
+    Xn, Xg = _mix(m, d, 7, seed=100 + d)
+    flat = torch.zeros(m * d + 1, dtype=torch.float32, device="cuda")
+    flat[1:] = Xg.reshape(-1)
+    Xmis = flat[1:].view(m, d)
+    assert Xmis.data_ptr() % 16 != 0
+    rng = np.random.default_rng(d)
+    Cn = (Xn[rng.integers(0, m, size=k)] + rng.normal(0, 0.3, size=(k, d))).astype(np.float32)
+    C = torch.from_numpy(Cn).cuda()
+    la, ca, sa = hp.assign_sse(Xg, C, precision=prec)
+    lm, cm, sm = hp.assign_sse(Xmis, C, precision=prec)
+    assert torch.equal(la, lm) and torch.equal(ca, cm) and sa.item() == sm.item()
+    o = orc.assign_sse(Xn, Cn.astype(np.float64), want_margins=True)
+    assert_labels(lm.cpu().numpy(), o["labels"], o["margins"])
+    assert rel(sm.item(), o["sse"]) <= SSE_REL
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_assign_sse_small_and_ragged(hp, orc, prec):
     for m, k in [(1, 1), (5, 3), (257, 2), (1023, 40), (77, 200)]:
         Xn, Xg = _mix(m, 5, 3, seed=m)
