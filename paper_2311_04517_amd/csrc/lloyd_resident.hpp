@@ -741,7 +741,9 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
                     const float xn2 = point_norm2<D>(xq);
                     const float xn = cert_norm(xn2);
                     const float h = screen_shift(xn2, xn, ea, eb);
-                    const Top3 t3 = screen_tile<D, PREC>(xq, L.aop, L.nrm, nblk, h, kmask);
+                    // (rows of 64 and more run at two waves per SIMD, with
+                    // the registers to interleave two blocks' MFMA chains)
+                    const Top3 t3 = screen_tile<D, PREC, (D >= 64)>(xq, L.aop, L.nrm, nblk, h, kmask);
                     const bool ok = certified(t3, kmask, qscale, xn, ea, eb) || !valid;
                     const int a1 = (int)key_index(t3.t1, kmask), a2 = (int)key_index(t3.t2, kmask);
                     const int am = redecide64<D, PREC>(

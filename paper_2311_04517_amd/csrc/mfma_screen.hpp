@@ -60,6 +60,8 @@
 // one of the two best, and on any row j that j is not the argmin.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace hpc {
@@ -259,69 +261,162 @@ __device__ __forceinline__ void split_point(const float (&xq)[Lay<D>::DL],
 
 // Keys of this lane's point against all nblk*16 centroids; returns the
 // merged three best (identical in the point's four lanes).  h: the point's
-// shifted norm from screen_shift.
-template <int D, int PREC>
+// shifted norm from screen_shift.  PAIRED takes the blocks in pairs with
+// their MFMA chains interleaved, so that one block's dependent products do
+// not wait on each other alone (for kernels at two waves per SIMD, where
+// little else hides that latency, and with the registers for a second
+// accumulator); the keys are inserted in block order either way, so the
+// result is the same.
+template <int D, int PREC, bool PAIRED = false>
 __device__ __forceinline__ Top3 screen_tile(const float (&xq)[Lay<D>::DL],
                                             const void* __restrict__ aop,
                                             const float* __restrict__ nrm, int nblk, float h,
                                             unsigned kmask) {
-    constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
-    const int lane = threadIdx.x & 63, g = lane >> 4;
-    Top3 t{~0u, ~0u, ~0u};
-    if constexpr (PREC == kPrecF32) {
-        const float* a = static_cast<const float*>(aop);
-        for (int blk = 0; blk < nblk; ++blk) {
-            f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+    if constexpr (!PAIRED) {
+        constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
+        const int lane = threadIdx.x & 63, g = lane >> 4;
+        Top3 t{~0u, ~0u, ~0u};
+        if constexpr (PREC == kPrecF32) {
+            const float* a = static_cast<const float*>(aop);
+            for (int blk = 0; blk < nblk; ++blk) {
+                f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
 #pragma unroll
-            for (int q = 0; q < DL; ++q)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
-                                                           acc, 0, 0, 0);
+                for (int q = 0; q < DL; ++q)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[(blk * DL + q) * 64 + lane], xq[q],
+                                                               acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
-        }
-    } else if constexpr (PREC == kPrecBF16x3) {
-        bf16x8 xh[KC], xl[KC];
-        split_point<D>(xq, xh, xl);
-        const bf16x8* a = static_cast<const bf16x8*>(aop);
-        const bf16x8* al = a + nblk * KC * 64;
-        for (int blk = 0; blk < nblk; ++blk) {
-            f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const int o = (blk * KC + kc) * 64 + lane;
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[o], xh[kc], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xl[kc], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xh[kc], acc, 0, 0, 0);
+                for (int r = 0; r < 4; ++r)
+                    top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
             }
+        } else if constexpr (PREC == kPrecBF16x3) {
+            bf16x8 xh[KC], xl[KC];
+            split_point<D>(xq, xh, xl);
+            const bf16x8* a = static_cast<const bf16x8*>(aop);
+            const bf16x8* al = a + nblk * KC * 64;
+            for (int blk = 0; blk < nblk; ++blk) {
+                f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
-        }
-    } else {
-        bf16x8 xb[KC];
+                for (int kc = 0; kc < KC; ++kc) {
+                    const int o = (blk * KC + kc) * 64 + lane;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[o], xh[kc], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xl[kc], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xh[kc], acc, 0, 0, 0);
+                }
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const int q = kc * 8 + v;
-                xb[kc][v] = (__bf16)(q < DL ? xq[q < DL ? q : 0] : 0.f);
+                for (int r = 0; r < 4; ++r)
+                    top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
             }
-        const bf16x8* a = static_cast<const bf16x8*>(aop);
-        for (int blk = 0; blk < nblk; ++blk) {
-            f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+        } else {
+            bf16x8 xb[KC];
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc)
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[(blk * KC + kc) * 64 + lane], xb[kc],
-                                                              acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int q = kc * 8 + v;
+                    xb[kc][v] = (__bf16)(q < DL ? xq[q < DL ? q : 0] : 0.f);
+                }
+            const bf16x8* a = static_cast<const bf16x8*>(aop);
+            for (int blk = 0; blk < nblk; ++blk) {
+                f32x4 acc = *reinterpret_cast<const f32x4*>(nrm + blk * 16 + 4 * g);
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[(blk * KC + kc) * 64 + lane], xb[kc],
+                                                                  acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
+            }
+        }
+        top3_merge<16>(t);
+        top3_merge<32>(t);
+        return t;
+    } else {
+        constexpr int DL = Lay<D>::DL, KC = Lay<D>::KC;
+        constexpr int PAIR = PAIRED ? 2 : 1;
+        const int lane = threadIdx.x & 63, g = lane >> 4;
+        Top3 t{~0u, ~0u, ~0u};
+        bf16x8 xh[KC], xl[KC];
+        if constexpr (PREC == kPrecBF16x3) {
+            split_point<D>(xq, xh, xl);
+        } else if constexpr (PREC == kPrecBF16) {
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int q = kc * 8 + v;
+                    xh[kc][v] = (__bf16)(q < DL ? xq[q < DL ? q : 0] : 0.f);
+                }
+        }
+        // the screened scores of NB consecutive blocks from blk on, their MFMA
+        // chains interleaved
+        auto scores = [&](int blk, auto nbc, f32x4 (&acc)[decltype(nbc)::value]) {
+            constexpr int NB = decltype(nbc)::value;
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                acc[u] = *reinterpret_cast<const f32x4*>(nrm + (blk + u) * 16 + 4 * g);
+            if constexpr (PREC == kPrecF32) {
+                const float* a = static_cast<const float*>(aop);
+#pragma unroll
+                for (int q = 0; q < DL; ++q)
+#pragma unroll
+                    for (int u = 0; u < NB; ++u)
+                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            a[((blk + u) * DL + q) * 64 + lane], xq[q], acc[u], 0, 0, 0);
+            } else if constexpr (PREC == kPrecBF16x3) {
+                const bf16x8* a = static_cast<const bf16x8*>(aop);
+                const bf16x8* al = a + nblk * KC * 64;
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int o = ((blk + u) * KC + kc) * 64 + lane;
+                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[o], xh[kc], acc[u], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int o = ((blk + u) * KC + kc) * 64 + lane;
+                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xl[kc], acc[u], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int o = ((blk + u) * KC + kc) * 64 + lane;
+                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[o], xh[kc], acc[u], 0, 0, 0);
+                    }
+                }
+            } else {
+                const bf16x8* a = static_cast<const bf16x8*>(aop);
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                    for (int u = 0; u < NB; ++u)
+                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[((blk + u) * KC + kc) * 64 + lane], xh[kc], acc[u], 0, 0, 0);
+            }
+        };
+        int blk = 0;
+        if constexpr (PAIR == 2) {
+            for (; blk + 1 < nblk; blk += 2) {
+                f32x4 acc[2];
+                scores(blk, std::integral_constant<int, 2>{}, acc);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        top3_insert(t, screen_key(acc[u][r] + h, kmask,
+                                                  (unsigned)((blk + u) * 16 + 4 * g + r)));
+            }
+        }
+        for (; blk < nblk; ++blk) {
+            f32x4 acc[1];
+            scores(blk, std::integral_constant<int, 1>{}, acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                top3_insert(t, screen_key(acc[r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
+                top3_insert(t, screen_key(acc[0][r] + h, kmask, (unsigned)(blk * 16 + 4 * g + r)));
         }
+        top3_merge<16>(t);
+        top3_merge<32>(t);
+        return t;
     }
-    top3_merge<16>(t);
-    top3_merge<32>(t);
-    return t;
 }
 
 // |x|^2 of this lane's point (same value in its four lanes).  Used by the
