@@ -68,6 +68,25 @@ namespace hpc {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// BF16 head and tail of two FP32 values: the head is x rounded to BF16
+// (nearest, ties to even), the tail x minus the head (exact in FP32) rounded
+// to BF16.  The heads are
+// converted as one pair and widened back to FP32 by shifting and masking
+// the packed pair, which spares a second conversion per value.
+// Lanes v and v + 1 of h and t receive those of x0 and x1.
+__device__ __forceinline__ void split2(float x0, float x1, bf16x8& h, bf16x8& t, int v) {
+    const bf16x2v hp = __builtin_convertvector((f32x2v){x0, x1}, bf16x2v);
+    const unsigned u = __builtin_bit_cast(unsigned, hp);
+    const float w0 = __uint_as_float(u << 16), w1 = __uint_as_float(u & 0xffff0000u);
+    const bf16x2v tp = __builtin_convertvector((f32x2v){x0 - w0, x1 - w1}, bf16x2v);
+    h[v] = hp[0];
+    h[v + 1] = hp[1];
+    t[v] = tp[0];
+    t[v + 1] = tp[1];
+}
 
 enum : int { kPrecF32 = 0, kPrecBF16 = 1, kPrecBF16x3 = 2 };
 
@@ -250,12 +269,11 @@ __device__ __forceinline__ void split_point(const float (&xq)[Lay<D>::DL],
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
+        for (int v = 0; v < 8; v += 2) {
             const int q = kc * 8 + v;
-            const float x = q < DL ? xq[q < DL ? q : 0] : 0.f;
-            const __bf16 hi = (__bf16)x;
-            xh[kc][v] = hi;
-            xl[kc][v] = (__bf16)(x - (float)hi);
+            const float x0 = q < DL ? xq[q < DL ? q : 0] : 0.f;
+            const float x1 = q + 1 < DL ? xq[q + 1 < DL ? q + 1 : 0] : 0.f;
+            split2(x0, x1, xh[kc], xl[kc], v);
         }
 }
 

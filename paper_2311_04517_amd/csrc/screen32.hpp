@@ -146,12 +146,16 @@ __device__ __forceinline__ f32x16 block_scores32(const float (&xh)[Lay32<D>::DH]
         for (int kc = 0; kc < KC; ++kc) {
             bf16x8 xb, xl;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) {
+            for (int v = 0; v < 8; v += 2) {
                 const int q = kc * 8 + v;
-                const float x = q < DH ? xh[q < DH ? q : 0] : 0.f;
-                const __bf16 hi = (__bf16)x;
-                xb[v] = hi;
-                if (PREC == kPrecBF16x3) xl[v] = (__bf16)(x - (float)hi);
+                const float x0 = q < DH ? xh[q < DH ? q : 0] : 0.f;
+                const float x1 = q + 1 < DH ? xh[q + 1 < DH ? q + 1 : 0] : 0.f;
+                if constexpr (PREC == kPrecBF16x3) {
+                    split2(x0, x1, xb, xl, v);
+                } else {
+                    xb[v] = (__bf16)x0;
+                    xb[v + 1] = (__bf16)x1;
+                }
             }
             const int o = (blk * KC + kc) * 64 + lane;
             if constexpr (PREC == kPrecBF16x3) {
