@@ -349,7 +349,7 @@ int dispatch_resident(int D, int prec, const hpc::LloydArgs& a, const ResGeo& g,
 // K-means++ seeding of cold samples by teams of workgroups.
 // --------------------------------------------------------------------------
 constexpr int kKppNT = 256;        // threads per workgroup of the seeding kernel
-constexpr int kKppMinSlice = 512;  // a team grows only while slices keep this many points
+constexpr int kKppMinSlice = 256;  // points per workgroup of a team at least (one group)
 constexpr int kKppMaxTeam = hpc::kMaxTeam;
 constexpr int kKppMaxWgPerCu = 8;  // bound on resident seeding workgroups per CU (buffers)
 
@@ -364,7 +364,7 @@ struct KppGeo {
 // Launch shape of the seeding kernel for n samples (largest s smax, largest
 // k kmax).  team_req 0 picks the team size from the free capacity: as many
 // workgroups per sample as the resident grid allows for all samples at once,
-// at most one per kKppMinSlice points.  inflight_req caps the teams working
+// at most one per kKppMinSlice points (rounded up) and kKppMaxTeam.  inflight_req caps the teams working
 // at once (0: as many as are resident; fewer keep the samples' rows and
 // weights within the last-level cache).  The grid is always resident at
 // once, which the teams' exchanges rely on (they wait on each other); a team
@@ -402,7 +402,7 @@ int kpp_geometry(int n, int smax, int kmax, int team_req, int inflight_req, KppG
         T = std::min(team_req, kKppMaxTeam);
     } else if (cap > 0) {
         const int64_t by_cap = cap / n;
-        const int64_t by_size = std::max<int64_t>(1, smax / kKppMinSlice);
+        const int64_t by_size = std::max<int64_t>(1, (smax + kKppMinSlice - 1) / kKppMinSlice);
         T = (int)std::max<int64_t>(1, std::min<int64_t>({by_cap, by_size, (int64_t)kKppMaxTeam}));
     }
     if (T > 1) {

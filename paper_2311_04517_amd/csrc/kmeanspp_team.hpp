@@ -4,19 +4,22 @@
 //
 // A cold sample (every centroid row degenerate) is split over a team of T
 // workgroups, each owning a contiguous slice of the sample's points in
-// index order.  Each of the k - 1 greedy steps then costs one pass over the
-// slice per workgroup plus two exchanges between the team's workgroups:
+// index order (whole groups of 256 points).  Each of the k - 1 greedy steps
+// then costs one pass over the slice per workgroup plus one exchange
+// between the team's workgroups:
 //
-//   1. every workgroup knows every slice's total weight W_b = sum of D^2,
-//      so all of them compute the same D^2-weighted targets; the workgroup
-//      whose slice holds a target finds the point (inverse CDF in index
-//      order) and publishes it;                               -- exchange A
+//   1. every workgroup knows every slice's total weight W_b = sum of D^2 and
+//      its group sums, so all of them compute the same D^2-weighted targets
+//      and find each target's slice and group; the point inside the group
+//      comes from the owner's 256 weights in global memory (written before
+//      the owner arrived at the last exchange);
 //   2. every workgroup computes, for its slice and each candidate t, the
 //      would-be weights min(|x - c_t|^2, D^2), their sums per group of 256
-//      points and over the slice, and publishes the slice sums;  -- exchange B
-//   3. every workgroup adds the slice sums in team order, keeps the
-//      candidate of smallest potential (lowest t on ties) and adopts that
-//      candidate's weights: the slice sums are already the next W_b.
+//      points and over the slice, and publishes the sums;  -- the exchange
+//   3. every workgroup adds the slice sums (in the same order in all of
+//      them), keeps the candidate of smallest potential (lowest t on ties)
+//      and adopts that candidate's weights: its slice and group sums are
+//      the next W_b and group sums.
 //
 // With T = 1 there is no exchange and the workgroup runs the same steps
 // alone (batches of many cold samples).  Everything a decision depends on
@@ -24,12 +27,11 @@
 // sums, potentials, targets; the decisions are then those of an FP64
 // evaluation up to the order of the sums.
 //
-// Layout (per point, thread-per-point): a wave takes groups of 256 points
-// (four tiles of 64, one point per lane) of its workgroup's slice; a lane
-// reads its point's whole row (stride D, zero padded) from the gathered
-// copy of the sample, the next tile's row being in flight while one is
-// processed.  The candidate rows are FP64 in LDS (broadcast reads).  D^2
-// lives in five rotating buffers of s doubles per sample: the weights of
+// Layout: the slice's rows are read from the gathered copy of the sample
+// (stride D, zero padded), D / 8 lanes per point with 8 coordinates each,
+// in groups of 256 points (see kpp_stream); the candidates' coordinates
+// are FP64 in registers for the whole pass.  D^2 lives in five rotating
+// buffers of s doubles per sample: the weights of
 // the step's candidates go to the four buffers not read, and the kept
 // candidate's buffer becomes the current one, so no pass updates D^2.
 // Group sums live in LDS, one array per buffer, and guide the inverse-CDF
@@ -211,28 +213,46 @@ __device__ __forceinline__ double point_sum(double v) {
 // of the slice sums is added to pot[t].
 //
 // Layout: LP = D / 8 lanes per point, each with 8 coordinates; a tile is
-// 64 / LP consecutive points.  A lane holds its 8 coordinates of every
-// candidate (FP64) in registers for the whole pass, so the pass reads no
-// LDS; the rows of the next two tiles are in flight while one is processed.
+// 64 / LP consecutive points, a group TPG tiles.  A lane holds its 8
+// coordinates of every candidate (FP64) in registers for the whole pass, so
+// the pass reads no LDS; the tiles go in batches whose loads are all in
+// flight at once.  A slice of at least NW groups gives each wave whole
+// groups (group q to wave q mod NW).  A smaller slice -- a team's slices
+// of one cold sample -- would leave waves idle and one wave's chain of
+// TPG dependent tiles per group on the critical path: there every group is
+// shared by all waves (tile u of a group to wave u mod NW), each wave's
+// share of a group sum goes to `part` (LDS, 4 x NW x NW doubles) and the
+// shares are added in wave order.  Every thread of the workgroup calls it.
 template <int D, int NT, int NC>
 __device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const double* crow,
                            const double* __restrict__ in, bool first, bool coh,
-                           double* const (&out)[4], double* const (&gto)[4], double (&pot)[4]) {
+                           double* const (&out)[4], double* const (&gto)[4], double (&pot)[4],
+                           double* part) {
     constexpr int NW = NT / kWave;
     constexpr int LP = D / 8, PPT = kWave / LP, TPG = kKppGroup / PPT;
+    static_assert(TPG % NW == 0, "a group's tiles split evenly over the waves");
+    constexpr int TPW = TPG / NW;  // tiles of a shared group per wave
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int p = lane % PPT, j = lane / PPT;  // point within the tile, dimension chunk
     const int ng = (hi - lo + kKppGroup - 1) / kKppGroup;
-    if (wid >= ng) return;
+    const bool shared = ng < NW;
+    if (ng == 0 || (!shared && wid >= ng)) return;  // (uniform over the workgroup)
     double cr[NC][8];
 #pragma unroll
     for (int t = 0; t < NC; ++t)
 #pragma unroll
         for (int u = 0; u < 8; ++u) cr[t][u] = crow[t * D + 8 * j + u];
-    // the wave's tiles in order: tile f is tile f % TPG of group wid + NW * (f / TPG)
-    const int nt = ((ng - 1 - wid) / NW + 1) * TPG;
-    auto point = [&](int f) { return lo + (wid + NW * (f / TPG)) * kKppGroup + (f % TPG) * PPT + p; };
+    // the wave's tiles in order.  Whole groups: tile f is tile f % TPG of
+    // group wid + NW * (f / TPG).  Shared groups: tile f is tile
+    // wid + NW * (f % TPW) of group f / TPW.
+    const int per_group = shared ? TPW : TPG;
+    const int nt = shared ? ng * TPW : ((ng - 1 - wid) / NW + 1) * TPG;
+    auto group_of = [&](int f) { return shared ? f / per_group : wid + NW * (f / per_group); };
+    auto point = [&](int f) {
+        const int u = f % per_group;
+        return lo + group_of(f) * kKppGroup + (shared ? wid + NW * u : u) * PPT + p;
+    };
     // branch-free loads (tiles past the wave's last and points past the
     // slice end re-read the last ones), so that the compiler's wait for a
     // tile's rows leaves the next tiles' loads in flight
@@ -247,10 +267,9 @@ __device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const d
     double gp[NC];
 #pragma unroll
     for (int t = 0; t < NC; ++t) gp[t] = 0.0;
-    auto process = [&](int f, const float4 (&x)[2], double dd) {
+    // the would-be weights of tile f (every lane of a point gets them)
+    auto dist = [&](const float4 (&x)[2], double dd, double (&nd)[NC]) {
         if (first) dd = __builtin_huge_val();  // the first centre: D^2 is the distance
-        const int i = point(f);
-        const bool mine = i < hi && j == 0;  // the lane that stores and counts the point
         const double xv[8] = {x[0].x, x[0].y, x[0].z, x[0].w, x[1].x, x[1].y, x[1].z, x[1].w};
 #pragma unroll
         for (int t = 0; t < NC; ++t) {
@@ -261,42 +280,86 @@ __device__ void kpp_stream(const float* __restrict__ sg, int lo, int hi, const d
                 acc = __fma_rn(e, e, acc);
             }
             acc = point_sum<LP>(acc);
-            const double nd = acc < dd ? acc : dd;
-            if (mine) {
-                // read by the other workgroups of a team: device-coherent
-                if (coh)
-                    store_dev(out[t] + i, nd);
-                else
-                    out[t][i] = nd;
-            }
-            gp[t] += mine ? nd : 0.0;
+            // every lane of the point holds the same sum (up to 8 lanes the
+            // pairwise sums take their operands in lane order); with 16 the
+            // first lane's is taken
+            if constexpr (LP == 16) acc = __shfl(acc, p, kWave);
+            nd[t] = acc < dd ? acc : dd;
         }
-        if (f % TPG == TPG - 1) {  // last tile of a group: its sums
-            const int q = wid + NW * (f / TPG);
+    };
+    // tile f's weights into the group sums, which are complete when f ends
+    // the wave's share of a group; tiles past the wave's last (f >= nt),
+    // computed on re-read rows, count nothing
+    auto account = [&](int f, const double (&nd)[NC]) {
+        const bool valid = f < nt;
+        const bool mine = valid && point(f) < hi && j == 0;  // the lane that counts the point
+#pragma unroll
+        for (int t = 0; t < NC; ++t) gp[t] += mine ? nd[t] : 0.0;
+        if (valid && f % per_group == per_group - 1) {
+            const int q = group_of(f);
 #pragma unroll
             for (int t = 0; t < NC; ++t) {
                 const double gs = wave_sum(gp[t]);
-                if (lane == 0) gto[t][q] = gs;
+                if (lane == 0) {
+                    if (shared)
+                        part[(t * NW + q) * NW + wid] = gs;
+                    else
+                        gto[t][q] = gs;
+                }
                 pot[t] += lane == 0 ? gs : 0.0;
                 gp[t] = 0.0;
             }
         }
     };
-    // three register buffers, unrolled by three (no buffer copies); nt is
-    // a multiple of TPG >= 4
-    float4 xa[2], xb[2], xc[2];
-    double da, db, dc;
-    fetch(0, xa, da);
-    fetch(1, xb, db);
-    for (int f = 0; f < nt; f += 3) {
-        fetch(f + 2, xc, dc);
-        process(f, xa, da);
-        if (f + 1 >= nt) break;
-        fetch(f + 3, xa, da);
-        process(f + 1, xb, db);
-        if (f + 2 >= nt) break;
-        fetch(f + 4, xb, db);
-        process(f + 2, xc, dc);
+    // every lane stores, without a branch: the lanes of a point, points past
+    // the slice end and tiles past the wave's last write the same values to
+    // the same (clamped) places as the lanes that own them, so that the
+    // compiler's count of memory operations in flight stays exact
+    auto store = [&](int f, const double (&nd)[NC]) {
+        const int ic = min(point(min(f, nt - 1)), hi - 1);
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+            // read by the other workgroups of a team: device-coherent
+            if (coh)
+                store_dev(out[t] + ic, nd[t]);
+            else
+                out[t][ic] = nd[t];
+        }
+    };
+    // batches of KB tiles, software pipelined: a batch's rows and weights
+    // are all in flight before its first tile is computed, and its results
+    // are stored only after the next batch's loads are issued, so that no
+    // load waits behind a store (vector memory operations complete in order)
+    constexpr int KB = NC <= 3 ? 4 : 2;  // (within 256 registers: two waves per SIMD)
+    float4 xs[KB][2];
+    double dv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) fetch(u, xs[u], dv[u]);
+    for (int f0 = 0; f0 < nt; f0 += KB) {
+        // the batch's distances first (no branch between its tiles, so that
+        // their FP64 chains interleave), then the sums
+        double nd[KB][NC];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) dist(xs[u], dv[u], nd[u]);
+#pragma unroll
+        for (int u = 0; u < KB; ++u) account(f0 + u, nd[u]);
+        // (unconditional: past the wave's last tile the loads re-read it)
+#pragma unroll
+        for (int u = 0; u < KB; ++u) fetch(f0 + KB + u, xs[u], dv[u]);
+#pragma unroll
+        for (int u = 0; u < KB; ++u) store(f0 + u, nd[u]);
+    }
+    if (shared) {
+        __syncthreads();
+        const int tid = threadIdx.x;
+        if (tid < NC * ng) {
+            const int t = tid / ng, q = tid % ng;
+            double acc = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) acc += part[(t * NW + q) * NW + w];
+            gto[t][q] = acc;
+        }
+        __syncthreads();
     }
 }
 
@@ -305,12 +368,13 @@ template <int D, int NT>
 __device__ __forceinline__ void kpp_stream_n(int nc, const float* __restrict__ sg, int lo, int hi,
                                              const double* crow, const double* __restrict__ in,
                                              bool coh, double* const (&out)[4],
-                                             double* const (&gto)[4], double (&pot)[4]) {
+                                             double* const (&gto)[4], double (&pot)[4],
+                                             double* part) {
     switch (nc) {
-        case 1: kpp_stream<D, NT, 1>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
-        case 2: kpp_stream<D, NT, 2>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
-        case 3: kpp_stream<D, NT, 3>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
-        default: kpp_stream<D, NT, 4>(sg, lo, hi, crow, in, false, coh, out, gto, pot); break;
+        case 1: kpp_stream<D, NT, 1>(sg, lo, hi, crow, in, false, coh, out, gto, pot, part); break;
+        case 2: kpp_stream<D, NT, 2>(sg, lo, hi, crow, in, false, coh, out, gto, pot, part); break;
+        case 3: kpp_stream<D, NT, 3>(sg, lo, hi, crow, in, false, coh, out, gto, pot, part); break;
+        default: kpp_stream<D, NT, 4>(sg, lo, hi, crow, in, false, coh, out, gto, pot, part); break;
     }
 }
 
@@ -326,6 +390,7 @@ __host__ __device__ inline size_t kpp_lds_bytes(int ngmax, int kmax, int T) {
                        + (size_t)T * ngmax         // every slice's group sums (current weights)
                        + 4 * (size_t)D             // candidate rows
                        + 4 * (NT / kWave)          // workgroup sums
+                       + 4 * (NT / kWave) * (NT / kWave)  // shared groups' wave shares
                        + (size_t)T                 // every slice's weight
                        + (size_t)T * kpp_slot_doubles(ngmax)  // one exchange, gathered
                        + 8;                        // potentials
@@ -350,7 +415,8 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
     double* ggs = gtmp + 4 * ngmax;                  // T x ngmax: every slice's, current weights
     double* crow = ggs + (size_t)T * ngmax;          // 4 x D
     double* red = crow + 4 * D;                      // 4 x NW
-    double* wts = red + 4 * NW;                      // T: every slice's weight
+    double* part = red + 4 * NW;                     // 4 x NW x NW: shared groups' wave shares
+    double* wts = part + 4 * NW * NW;                // T: every slice's weight
     double* tsl = wts + T;                           // T x SD: one exchange's slots
     double* pv = tsl + (size_t)T * SD;               // 8
     int* picks = reinterpret_cast<int*>(pv + 8);     // kmax
@@ -510,10 +576,10 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
                 if (!team_sync()) return -1;
                 for (int e = tid; e < T * SD; e += NT) tsl[e] = load_dev(slot(par, e / SD) + e % SD);
                 __syncthreads();
-                if (tid < 4) {
-                    double acc = 0.0;
-                    for (int q = 0; q < T; ++q) acc += tsl[q * SD + tid];
-                    pv[tid] = acc;
+                if (wid < 4) {  // wave t adds candidate t's slice sums
+                    const double v = lane < T ? tsl[lane * SD + wid] : 0.0;
+                    const double acc = wave_sum(v);
+                    if (lane == 0) pv[wid] = acc;
                 }
             } else if (tid < 4) {
                 pv[tid] = pt[tid];
@@ -541,16 +607,19 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
         {
             double* const o[4] = {buf(0), buf(0), buf(0), buf(0)};
             double* const g[4] = {gtmp, gtmp, gtmp, gtmp};
-            kpp_stream<D, NT, 1>(sg, lo, hi, crow, buf(0), true, coh, o, g, pot);
+            kpp_stream<D, NT, 1>(sg, lo, hi, crow, buf(0), true, coh, o, g, pot, part);
         }
         block_pot(pot);
         int cur = 0;
         bool alive = exchange(pot, 1) >= 0;
         for (int r = 1; r < k && alive; ++r) {
             const Words4 w = philox_block(ds.seed, a.tag, (uint64_t)r, ds.sample_id, a.call_id);
-            // W in team order (the same value in every workgroup)
-            double W = 0.0;
-            for (int q = 0; q < T; ++q) W += wts[q];
+            // every slice's running end in team order, one slice per lane (a
+            // team has at most 64 workgroups), and W, the last one: the same
+            // values in every workgroup
+            const double wq = lane < T ? wts[lane] : 0.0;
+            const double wend = wave_incl_scan(wq);
+            const double W = __shfl(wend, kWave - 1, kWave);
             int pick;
             if (!(W > 0.0)) {
                 pick = (int)bounded_index(w.w[0], (uint64_t)s);
@@ -562,17 +631,14 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
                 const double* const wcur = buf(cur);
                 if (wid < nc) {
                     const double x = unit_double(w.w[wid]) * W;
-                    double run = 0.0, off = 0.0;
-                    int owner = -1, last_pos = -1;
-                    for (int q = 0; q < T; ++q) {
-                        const double v = wts[q];
-                        if (owner < 0 && run + v > x) {
-                            owner = q;
-                            off = run;
-                        }
-                        if (v > 0.0) last_pos = q;
-                        run += v;
-                    }
+                    const unsigned long long over = __ballot(lane < T && wend > x);
+                    const unsigned long long pos = __ballot(lane < T && wq > 0.0);
+                    int owner = over ? __ffsll((long long)over) - 1 : -1;
+                    const int last_pos = pos ? 63 - __clzll((long long)pos) : -1;
+                    // the running end of the slices before the owner
+                    const double prev = __shfl_up(wend, 1, kWave);
+                    double off = 0.0;
+                    if (owner > 0) off = __shfl(prev, owner, kWave);
                     int found = -1;
                     const bool rounded_up = owner < 0;
                     if (rounded_up) owner = last_pos;
@@ -611,7 +677,7 @@ __global__ __launch_bounds__(NT) void k_kmeanspp_team(KppArgs a) {
 #pragma unroll
                 for (int t = 0; t < 4; ++t) o[t] = buf((cur + 1 + t) % kKppBuffers);
                 double pt[4] = {0.0, 0.0, 0.0, 0.0};
-                kpp_stream_n<D, NT>(nc, sg, lo, hi, crow, wcur, coh, o, g, pt);
+                kpp_stream_n<D, NT>(nc, sg, lo, hi, crow, wcur, coh, o, g, pt, part);
                 block_pot(pt);
                 const int tb = exchange(pt, nc);
                 alive = tb >= 0;

@@ -245,13 +245,14 @@ def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed, prec):
     assert clean >= 5, "too few clean seeds"
 
 
-@pytest.mark.parametrize("team", [1, 2, 4, 8])
+@pytest.mark.parametrize("team", [1, 2, 4, 8, 16, 40])
 @pytest.mark.parametrize("d,s,k", [(8, 3000, 10), (32, 10_000, 25), (64, 6000, 40)])
 def test_cold_batch_seeding_teams(hp, orc, team, d, s, k):
-    """Cold samples seeded by teams of 1, 2, 4 and 8 workgroups (a plan's
-    seed_team), then Lloyd to the stop rule: pass counts, objectives,
-    centroids and labels against the oracle's cold start on the same
-    streams."""
+    """Cold samples seeded by teams of 1 to 40 workgroups (a plan's
+    seed_team; slices of fewer than four groups of 256 points, where the
+    waves share each group, from 4 workgroups on), then Lloyd to the stop
+    rule: pass counts, objectives, centroids and labels against the
+    oracle's cold start on the same streams."""
     m = 60_000
     Xn, Xg = _mix(m, d, 12, seed=500 + d)
     W = 4
@@ -510,15 +511,24 @@ def test_direct_reads_long_runs_and_reseed(hp, orc, prec):
         f, it, lab = hp.lloyd_batch(Xg, idx, desc, C, want_labels=True, precision=prec)
         outs.append((C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()))
     (Cg, fg, itg, lg), (Cm, fm, itm, lm) = outs
+    ros = [orc.lloyd(Xn, idx_n[b * s:(b + 1) * s], k, C0[b].astype(np.float64), seed=4,
+                     sample_id=b, want_margins=True) for b in range(n)]
     # the FP64 sums take LDS atomics in arrival order: agreement to rounding
-    assert np.array_equal(itg, itm) and np.array_equal(lg, lm)
-    assert np.allclose(fg, fm, rtol=1e-13, atol=0) and np.allclose(Cg, Cm, rtol=1e-6, atol=1e-6)
+    # on samples whose oracle run is clean (labels except at points within
+    # rounding of a tie)
+    for b in range(n):
+        if not diag_clean(ros[b].diag):
+            continue
+        sl, cl = slice(b * s, (b + 1) * s), slice(b * k * d, (b + 1) * k * d)
+        assert itg[b] == itm[b], (b, itg[b], itm[b])
+        assert_labels(lm[sl], lg[sl], ros[b].margins, what=f"sample {b}, aligned against gathered")
+        assert np.allclose(fg[b], fm[b], rtol=1e-13, atol=0)
+        assert np.allclose(Cg[cl], Cm[cl], rtol=1e-6, atol=1e-6)
     assert itg.max() > 15  # some runs outlast the direct-read passes
     checked = 0
     for b in range(n):
         ib = idx_n[b * s:(b + 1) * s]
-        ro = orc.lloyd(Xn, ib, k, C0[b].astype(np.float64), seed=4, sample_id=b,
-                       want_margins=True)
+        ro = ros[b]
         if b in (1, 5):
             assert ro.diag["n_seed_calls"] >= 1
         if not diag_clean(ro.diag):
@@ -551,15 +561,24 @@ def _shared_case(hp, orc, Xn, n, s, k, C0, seed, prec, *, min_long=0, reseeded=(
         outs.append((C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()))
     (Cg, fg, itg, lg), (Cm, fm, itm, lm) = outs
     assert np.isfinite(fg).all()
-    # shared and unshared runs differ only in the order the sums are added
-    assert np.array_equal(itg, itm) and np.array_equal(lg, lm)
-    assert np.allclose(fg, fm, rtol=1e-11, atol=0) and np.allclose(Cg, Cm, rtol=1e-6, atol=1e-6)
+    ros = [orc.lloyd(Xn, idx_n[b * s:(b + 1) * s], k, C0[b].astype(np.float64), seed=seed,
+                     sample_id=b, want_margins=True) for b in range(n)]
+    # shared and unshared runs differ only in the order the sums are added:
+    # agreement on samples whose oracle run is clean (labels except at
+    # points within rounding of a tie)
+    for b in range(n):
+        if not diag_clean(ros[b].diag):
+            continue
+        sl, cl = slice(b * s, (b + 1) * s), slice(b * k * d, (b + 1) * k * d)
+        assert itg[b] == itm[b], (b, itg[b], itm[b])
+        assert_labels(lm[sl], lg[sl], ros[b].margins, what=f"sample {b}, shared against unshared")
+        assert np.allclose(fg[b], fm[b], rtol=1e-11, atol=0)
+        assert np.allclose(Cg[cl], Cm[cl], rtol=1e-6, atol=1e-6)
     assert itg.max() >= min_long
     checked = 0
     for b in range(n):
         ib = idx_n[b * s:(b + 1) * s]
-        ro = orc.lloyd(Xn, ib, k, C0[b].astype(np.float64), seed=seed, sample_id=b,
-                       want_margins=True)
+        ro = ros[b]
         if b in reseeded:
             assert ro.diag["n_seed_calls"] >= 1
         if not diag_clean(ro.diag):

@@ -76,14 +76,26 @@ def test_plan_parts_beyond_the_resident_grid(hp, orc, prec, d, n, s, parts):
             outs.append((C.cpu().numpy(), f.cpu().numpy(), it.cpu().numpy(), lab.cpu().numpy()))
     (Cg, fg, itg, lg) = outs[0]
     assert np.isfinite(fg).all() and (itg > 0).all()
+    ros = [orc.lloyd(Xn, idx_n[b * s:(b + 1) * s], k, C0[b].astype(np.float64), seed=9,
+                     sample_id=b, want_margins=True) for b in range(n)]
+    # configurations differ only in the order the partial sums are added (the
+    # LDS sums in no fixed order): on samples where no decision of the
+    # oracle's run sits within rounding of its threshold they take the same
+    # decisions (labels may differ only at points within rounding of a tie);
+    # elsewhere a reseed draw or a stop test may go either way
+    clean = [b for b in range(n) if diag_clean(ros[b].diag)]
+    assert len(clean) >= n // 2
     for Co, fo, ito, lo in outs[1:]:
-        # configurations differ only in the order the partial sums are added
-        assert np.array_equal(itg, ito) and np.array_equal(lg, lo)
-        assert np.allclose(fg, fo, rtol=1e-11, atol=0) and np.allclose(Cg, Co, rtol=1e-6, atol=1e-6)
+        for b in clean:
+            sl, cl = slice(b * s, (b + 1) * s), slice(b * k * d, (b + 1) * k * d)
+            assert itg[b] == ito[b], (b, itg[b], ito[b])
+            assert_labels(lo[sl], lg[sl], ros[b].margins, what=f"sample {b} across configurations")
+            assert np.allclose(fg[b], fo[b], rtol=1e-11, atol=0)
+            assert np.allclose(Cg[cl], Co[cl], rtol=1e-6, atol=1e-6)
     checked = 0
     for b in range(n):
         ib = idx_n[b * s:(b + 1) * s]
-        ro = orc.lloyd(Xn, ib, k, C0[b].astype(np.float64), seed=9, sample_id=b, want_margins=True)
+        ro = ros[b]
         if b in (3, n - 2):
             assert ro.diag["n_seed_calls"] >= 1
         if not diag_clean(ro.diag):
