@@ -726,7 +726,8 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref, model=None):
     """Time until the incumbent's full-data SSE is within 1e-3 of the
     reference f_ref, for the plain single-worker form on the GPU and for
     batched forms (W workers per round: FP32, BF16 screening, BF16 plus the
-    learned initializer on the cold round).  Each form records an HIP event
+    learned initializer on the cold round; and BF16 with as few workers as
+    fill the GPU with one seeding team of a workgroup per 256 points each).  Each form records an HIP event
     and a copy of its incumbent after every incumbent update; SSEs are
     evaluated afterwards.  ``model``: the trained learned initializer (its
     form is skipped without one)."""
@@ -771,10 +772,16 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref, model=None):
     res["plain_fp32_per_sample"] = {"ms": t, "samples": None if i is None else i + 1,
                                     "sse": v, "ms_all": t_plain[-1]}
 
-    forms = [("batched_fp32", api.PREC_FP32, False), ("batched_bf16", api.PREC_BF16_MFMA, False)]
+    # the batched forms at the workload's W workers, and BF16 at as few
+    # workers as one team-seeded cold sample each fills the GPU with (each
+    # round then costs about one cold sample's latency)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    w_few = max(1, min(W, 2 * cus // max(1, -(-s // 256))))
+    forms = [("batched_fp32", api.PREC_FP32, False, W), ("batched_bf16", api.PREC_BF16_MFMA, False, W),
+             ("batched_bf16_few_workers", api.PREC_BF16_MFMA, False, w_few)]
     if model is not None:
-        forms.append(("batched_bf16_learned", api.PREC_BF16_MFMA, True))
-    for name, prec, use_learned in forms:
+        forms.append(("batched_bf16_learned", api.PREC_BF16_MFMA, True, W))
+    for name, prec, use_learned, W in forms:
         R = args.tts_rounds
         desc, idx_len, c_len = api.make_desc([s] * W, [k] * W, seed=args.seed,
                                              sample_id=range(W), d=d)
@@ -807,7 +814,7 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref, model=None):
         times = [evs[0].elapsed_time(e) for e in evs[1:]]
         sses = _sses(api, X, hist, prec)
         i, t, v = _first_reach(sses, times, target)
-        res[name] = {"ms": t, "rounds": None if i is None else i + 1, "sse": v,
+        res[name] = {"ms": t, "rounds": None if i is None else i + 1, "sse": v, "workers": W,
                      "ms_per_round": [round(x, 3) for x in np.diff([0.0] + times)]}
         if acc is not None:
             res[name]["accepted_frac"] = acc.float().mean().item()
@@ -815,6 +822,8 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref, model=None):
     best = res.get("batched_bf16_learned") or res["batched_bf16"]
     p = res["plain_fp32_per_sample"]["ms"]
     res["speedup_vs_plain"] = (p / best["ms"]) if (p and best["ms"]) else None
+    few = res["batched_bf16_few_workers"]["ms"]
+    res["speedup_vs_plain_few_workers"] = (p / few) if (p and few) else None
     return res
 
 
