@@ -286,7 +286,10 @@ typedef struct {
                           between waves); 0 = as many as fit in 64 KiB     */
     int32_t order;     /* 0: longest sample first; 1: descriptor order      */
     int32_t seed_team; /* workgroups per cold sample in the K-means++ seeding
-                          kernel, 0..64; 0 = chosen from the free capacity  */
+                          kernel, 0..64; 0 = chosen from the free capacity:
+                          every cold sample's team resident at once, at
+                          most one workgroup per 256 points of the largest
+                          sample                                          */
     int32_t seed_inflight; /* cold samples seeded at once at most (0 = as many
                           teams as are resident; fewer keep the samples'
                           rows and weights in the last-level cache)        */
