@@ -147,7 +147,8 @@ def _seed_case(hp, orc, Xn, Xg, s, k, seed, sid, call, Cin=None, n_cand=3):
     return Co, cho, g, Cg.cpu().numpy(), chg.cpu().numpy()
 
 
-@pytest.mark.parametrize("d,s,k", [(8, 2000, 10), (32, 10_000, 25), (5, 777, 7), (64, 3000, 40)])
+@pytest.mark.parametrize("d,s,k", [(8, 2000, 10), (32, 10_000, 25), (5, 777, 7), (64, 3000, 40),
+                                   (100, 5000, 20), (128, 2000, 12)])
 def test_seed_kmeanspp_bit_exact(hp, orc, d, s, k):
     Xn, Xg = _mix(40_000, d, 12, seed=100 + d)
     clean = 0
@@ -246,7 +247,7 @@ def test_lloyd_cold_start_end_to_end(hp, orc, d, s, k, mseed, prec):
 
 
 @pytest.mark.parametrize("team", [1, 2, 4, 8, 16, 40])
-@pytest.mark.parametrize("d,s,k", [(8, 3000, 10), (32, 10_000, 25), (64, 6000, 40)])
+@pytest.mark.parametrize("d,s,k", [(8, 3000, 10), (32, 10_000, 25), (64, 6000, 40), (128, 4000, 20)])
 def test_cold_batch_seeding_teams(hp, orc, team, d, s, k):
     """Cold samples seeded by teams of 1 to 40 workgroups (a plan's
     seed_team; slices of fewer than four groups of 256 points, where the
