@@ -13,6 +13,10 @@ of the best worker, and the full-data assignment with its FP64 objective.
 
 metric: sample-point-iters/s = sum over samples of s x assignment passes,
 divided by the wall time of the timed steps (inputs resident in HBM).
+Before the measured screening's autotuning and warm-up steps the process
+runs two untimed rounds of the same plan shape once (the first measurement
+in a process reads 6-9% slow otherwise; more warm-up steps do not remove
+that, one such dry run does).
 
 --workload precision runs the same rounds on the precision workload (m =
 10^8, d = 64, 100 rotated anisotropic components, k = 100, 128 workers of
@@ -190,6 +194,13 @@ def measure(api, X, args, copy, other_precision):
     W, s, k = args.workers, args.s, args.k
     prec = SCREENINGS[args.precision][0]
     args.error_workers = [0, W // 2] if args.error_report else None
+    # an untimed dry run of the same rounds first (no autotuning, two
+    # rounds): the first measurement in a process otherwise reads 6-9% slow
+    # (fresh device allocations; more warm-up rounds, two seconds of prior
+    # GPU load or a pause do not change it, one dry run does)
+    dry = argparse.Namespace(**vars(args))
+    dry.autotune, dry.warmup, dry.steps, dry.error_workers = False, 1, 2, None
+    run_metric(api, X, dry, prec, quiet=True)
     main_res = run_metric(api, X, args, prec)
     others = {}
     if other_precision:
@@ -308,9 +319,10 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
             "what": "1 GiB device-to-device copy (read + write bytes), best of 5, HIP events"}
 
 
-def run_metric(api, X, args, prec):
+def run_metric(api, X, args, prec, quiet=False):
     """The timed competitive rounds (see the module docstring) with one
-    screening precision: autotune, warm up, time args.steps rounds."""
+    screening precision: autotune, warm up, time args.steps rounds.
+    ``quiet``: print nothing (the untimed dry run)."""
     import numpy as np
     import torch
 
@@ -392,9 +404,10 @@ def run_metric(api, X, args, prec):
                 "unit": "sample-point-iters/s",
                 "what": f"first round: K-means++ seeding of all {W} samples, then passes to "
                         "the stop rule (seeding kernel + Lloyd kernel, HIP events)"}
-    print(f"[bench] {args.warmup} warmup step(s) done"
-          + (f"; cold round {cold['ms']:.2f} ms, {cold['passes']} passes" if cold else ""),
-          file=sys.stderr, flush=True)
+    if not quiet:
+        print(f"[bench] {args.warmup} warmup step(s) done"
+              + (f"; cold round {cold['ms']:.2f} ms, {cold['passes']} passes" if cold else ""),
+              file=sys.stderr, flush=True)
     its = []
     C_before = C_inc.clone()
     r_first_timed = args.warmup
@@ -411,10 +424,11 @@ def run_metric(api, X, args, prec):
     spi_per_step = passes.mean() * s
     lloyd_gbs = spi_per_step * 4 * d / t_lloyd / 1e9
     assign_gbs = (m * 4 * d + m * 4) / t_assign / 1e9
-    print(f"[bench] precision {prec}: {args.steps} steps in {elapsed:.3f}s; passes/step "
-          f"{passes.tolist()}; lloyd {t_lloyd * 1e3:.2f} ms ({lloyd_gbs:.0f} GB/s algorithmic), "
-          f"assign {t_assign * 1e3:.3f} ms ({assign_gbs:.0f} GB/s), SSE {sse.item():.6e}",
-          file=sys.stderr, flush=True)
+    if not quiet:
+        print(f"[bench] precision {prec}: {args.steps} steps in {elapsed:.3f}s; passes/step "
+              f"{passes.tolist()}; lloyd {t_lloyd * 1e3:.2f} ms ({lloyd_gbs:.0f} GB/s "
+              f"algorithmic), assign {t_assign * 1e3:.3f} ms ({assign_gbs:.0f} GB/s), "
+              f"SSE {sse.item():.6e}", file=sys.stderr, flush=True)
     # one more round after the timed ones, untimed, with sample labels: its
     # inputs and outputs feed the error report against the oracle
     check = None
