@@ -814,7 +814,8 @@ def time_to_sse(api, X, args, m, d, k, s, W, f_ref, model=None):
         f = torch.empty(W, dtype=torch.float64, device=dev)
         it = torch.empty(W, dtype=torch.int32, device=dev)
         # the untimed first run: a cold round of the same shape (and the
-        # learned seeding), then the sample ids and incumbents start afresh
+        # learned seeding) and a round, then the sample ids and incumbents
+        # start afresh
         C_inc = torch.full((c_len,), float("nan"), device=dev)
         f_inc = torch.full((W,), float("inf"), dtype=torch.float64, device=dev)
         plan.draw(m, idx)
