@@ -787,7 +787,18 @@ __global__ __launch_bounds__(NT, (D <= 32 && !SHARE) ? 4 : 2) void k_lloyd_resid
                                     lprev[(unsigned)i] = am;
                             }
                         }
-                        if (g == 0 && lab_out) lab_out[(unsigned)i] = am;
+                        if (g == 0 && lab_out) {
+                            // while shared, device-coherent as well: a plain
+                            // store would leave this part's L2 line dirty,
+                            // and its write-back could land after the labels
+                            // the first workgroup writes for the same points
+                            // once it continues alone (L2 lines span the
+                            // tiles of several parts)
+                            if (SHARE && paired)
+                                store_dev(lab_out + (unsigned)i, am);
+                            else
+                                lab_out[(unsigned)i] = am;
+                        }
                     }
                 };
                 if (gathered) {
